@@ -1,0 +1,105 @@
+"""Write the path fixtures used by the tracker tests and the benchmark.
+
+For each workload shape: draw the seeded system (``synth``), refine its
+planted root to the exact regular root z** in high precision
+(``oracle.track.refine_root``), track backward from z** to t = 0 in FP64 to
+name the start root x_v = exp(2 pi i k_v / d_v) whose path ends at z**, and
+confirm the pair by tracking forward.  Also stores the FP64 point of that
+path at t = 1/2 (a starting point for fixed-t Newton timing).
+
+Calls only ``oracle/`` and ``synth/``.  Usage:
+
+    python tests/golden/make_fixtures.py n8_dd n32_dd n64_qd n64_dd n128_dd
+"""
+
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle.numbers import to_limbs_complex  # noqa: E402
+from oracle.track import F64Homotopy, refine_root, start_root_index, track_f64  # noqa: E402
+from synth.systems import CONFIGS, config_system, make_system  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ZSS_LIMBS = 8  # 424 bits: far below the quad-double unit roundoff
+
+
+def fixture_for(sysm, name: str, meta: dict) -> dict:
+    t0 = time.time()
+    rr = refine_root(sysm, sysm.zstar)
+    t_ref = time.time() - t0
+    H = F64Homotopy(sysm)
+    zss64 = np.array([complex(v) for v in rr.z])
+    k, x0 = start_root_index(H, zss64)
+    start = np.exp(2j * np.pi * k / H.deg)
+    x_half, _ = track_f64(H, start, 0.0, 0.5)
+    x1, nsteps = track_f64(H, start, 0.0, 1.0)
+    fwd_err = float(np.max(np.abs(x1 - zss64)))
+    if fwd_err > 1e-8:
+        raise RuntimeError(f"{name}: forward FP64 track missed z** by {fwd_err}")
+    zss = [to_limbs_complex(v, ZSS_LIMBS).tolist() for v in rr.z]
+    out = dict(meta)
+    out.update(
+        {
+            "name": name,
+            "source": "written by tests/golden/make_fixtures.py from oracle.track (refine_root, FP64 tracker)",
+            "n": sysm.n,
+            "L": sysm.L,
+            "degrees": [int(d) for d in H.deg],
+            "start_k": [int(v) for v in k],
+            "zss_limbs": zss,
+            "refine_corrections": rr.corrections,
+            "fp64_forward_steps": int(nsteps),
+            "fp64_forward_err": fwd_err,
+            "x_half_f64": [[float(v.real), float(v.imag)] for v in x_half],
+            "seconds": time.time() - t0,
+            "refine_seconds": t_ref,
+        }
+    )
+    return out
+
+
+def main(names):
+    for name in names:
+        cfg = CONFIGS[name]
+        s = config_system(cfg)
+        meta = {"config": name, "m": cfg.m, "E": cfg.E, "seed": cfg.seed}
+        out = fixture_for(s, name, meta)
+        path = os.path.join(HERE, f"path_{name}.json")
+        with open(path, "w") as fh:
+            json.dump(out, fh, indent=1)
+        print(name, "k[:4] =", out["start_k"][:4], "seconds", round(out["seconds"], 1), flush=True)
+
+
+def main_family(prefix: str, n: int, m: int, E: int, L: int, seeds):
+    """Fixtures for a family of systems (learned step control): one JSON with all of them."""
+    rows = []
+    for seed in seeds:
+        s = make_system(n, m, E, L, seed)
+        try:
+            out = fixture_for(s, f"{prefix}_{seed}", {"seed": seed, "m": m, "E": E})
+        except RuntimeError as e:  # keep going; the family records which seeds failed
+            print("skip", seed, e, flush=True)
+            continue
+        out.pop("x_half_f64")
+        rows.append(out)
+        print(prefix, seed, round(out["seconds"], 1), flush=True)
+    with open(os.path.join(HERE, f"family_{prefix}.json"), "w") as fh:
+        json.dump(rows, fh)
+
+
+if __name__ == "__main__":
+    if len(sys.argv) > 1 and sys.argv[1] == "family":
+        # family <prefix> <first_seed> <count>
+        prefix, first, count = sys.argv[2], int(sys.argv[3]), int(sys.argv[4])
+        main_family(prefix, 32, 32, 3, 2, range(first, first + count))
+    else:
+        main(sys.argv[1:] or ["n8_dd", "n32_dd", "n64_qd", "n64_dd", "n128_dd"])
