@@ -1,0 +1,237 @@
+"""Benchmark: complex double-double Newton steps per second at n = 64.
+
+Workload: the n = 64 system (64 monomials per polynomial, exponents uniform
+in {0..4}, unit-circle coefficients, seed 2) stored in double double, the
+total-degree homotopy at t = 1/2, starting at the point of the tracked path
+at t = 1/2 (stored fixture).  One step = one Newton iteration of Algorithm
+4.1 = evaluation of h and its full Jacobian + Gaussian elimination with
+partial pivoting + back substitution + update, with the convergence exit
+disabled (eps = 0) so that every step does the full work.  Inputs are
+resident in HBM before the timed region; the timed region is K iterations
+enqueued back to back on one stream, bracketed by device synchronisation.
+
+Prints one JSON line (see the keys below).  ``--gpus N`` with N > 1 exits:
+this build runs on one GPU.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "complex-DD Newton steps/s at n=64; full-path time at 28 correct digits"
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
+HBM_PEAK_GBS = 8000.0
+
+# algorithmic flops per complex operation in double double, counted from the
+# textbook double-double formulas: complex multiply 80, add 40, fma 120
+CMUL, CADD, CFMA = 80, 40, 120
+
+
+def ge_cfma(n: int) -> int:
+    """Complex fused multiply-adds of elimination on [A b]: sum_{r=1}^{n-1} r (r+1)."""
+    return sum(r * (r + 1) for r in range(1, n))
+
+
+def bs_cfma(n: int) -> int:
+    return n * (n - 1) // 2
+
+
+def eval_ops(exps, offsets):
+    """(cmults, cadds) of one evaluation: per monomial with k active variables
+    and k2 of them with exponent >= 2: 4k + k2 - 5 products and k + 1 sums."""
+    import numpy as np
+
+    e = np.asarray(exps)
+    k = (e > 0).sum(axis=1)
+    k2 = (e > 1).sum(axis=1)
+    cm = np.where(k >= 2, 4 * k + k2 - 5, np.where(k == 1, k2 + 1, 0)).sum()
+    ca = (k + 1).sum()
+    return int(cm), int(ca)
+
+
+def path_point(fix, L):
+    import numpy as np
+
+    x = np.zeros((len(fix["x_half_f64"]), 2, L))
+    for v, (re, im) in enumerate(fix["x_half_f64"]):
+        x[v, 0, 0] = re
+        x[v, 1, 0] = im
+    return x
+
+
+def cpu_baseline(sysm, x, t, budget_s: float = 20.0):
+    """Time the oracle's Newton step (plain mpmath evaluation + lu_solve) on
+    this host, single process, on as many steps as fit in the budget (>= 1)."""
+    from oracle.newton import newton_step
+
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        newton_step(sysm.exps, sysm.coefs, sysm.poly_offsets, sysm.gamma, t, x, form="quotient")
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > budget_s * 0.5 or steps >= 50:
+            break
+    return {
+        "value": steps / el,
+        "unit": "Newton steps/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{steps} oracle Newton step(s) (mpmath at 488 bits: plain evaluation + lu_solve) of the same "
+                  f"n=64 double-double workload at t=0.5, single process, {el:.1f} s",
+    }
+
+
+def track_case(q, name, L):
+    """Full path of a stored workload: seconds and correct digits vs the stored z**."""
+    import mpmath
+    import numpy as np
+
+    from synth.systems import CONFIGS, config_system, start_root
+
+    with open(os.path.join(ROOT, "tests", "golden", f"path_{name}.json")) as fh:
+        fix = json.load(fh)
+    s = config_system(CONFIGS[name])
+    S = q.System.from_synth(s)
+    H = q.Homotopy(S, s.gamma)
+    x0 = start_root(np.array(fix["degrees"]), np.array(fix["start_k"]), L)
+    z, st, _ = q.track_path(H, x0, L)
+    with mpmath.workprec(800):
+        def val(limbs):
+            return mpmath.mpc(mpmath.fsum(mpmath.mpf(float(a)) for a in limbs[0]),
+                              mpmath.fsum(mpmath.mpf(float(a)) for a in limbs[1]))
+
+        err = max(abs(val(z[v]) - val(np.array(fix["zss_limbs"][v]))) for v in range(s.n))
+        nrm = max(mpmath.mpf(1), max(abs(val(np.array(w))) for w in fix["zss_limbs"]))
+        digits = 99 if err == 0 else int(mpmath.floor(-mpmath.log10(err / nrm)))
+    return {"workload": name, "seconds": round(st["seconds"], 4), "correct_digits": digits,
+            "succ_corrections": st["succ_corrections"], "corrections": st["corrections"],
+            "newton_iterations": st["newton_iterations"], "avg_step": st["avg_step"], "min_step": st["min_step"],
+            "fail": st["fail"]}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--mode", choices=["full", "mixed"], default="full")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-paths", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 256 MiB device copy (for HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    if args.copy_calibration:
+        a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8, "launches": 5}))
+        return
+
+    import paper_1109_0545_amd as q
+    from synth.systems import CONFIGS, config_system
+
+    cfg = CONFIGS["n64_dd"]
+    sysm = config_system(cfg)
+    with open(os.path.join(ROOT, "tests", "golden", "path_n64_dd.json")) as fh:
+        fix = json.load(fh)
+    L = 2
+    t = 0.5
+    x0 = path_point(fix, L)
+    S = q.System.from_synth(sysm)
+    H = q.Homotopy(S, sysm.gamma)
+    mode = q.SOLVE_FULL if args.mode == "full" else q.SOLVE_MIXED_IR
+    stream = torch.cuda.current_stream()
+    x = torch.from_numpy(x0).cuda()
+
+    # warmup (also converges onto the path point at t = 1/2)
+    q.newton_step_dev(H, t, x, L, mode, eps=0.0, max_it=args.warmup, stream=stream)
+    info_w = q.last_info(H, L, stream=stream)
+    torch.cuda.synchronize()
+
+    q.binding.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    q.newton_step_dev(H, t, x, L, mode, eps=0.0, max_it=args.steps, stream=stream)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    q.binding.set_timing(False)
+    info = q.last_info(H, L, stream=stream)
+    if info["iterations"] != args.steps:
+        raise RuntimeError(f"only {info['iterations']} of {args.steps} Newton iterations ran: {info}")
+    eval_ms, solve_ms, launches = q.binding.last_timing(H, L, stream=stream)
+
+    n = sysm.n
+    cm, ca = eval_ops(sysm.exps, sysm.poly_offsets)
+    ge_flops = (ge_cfma(n) + bs_cfma(n)) * CFMA
+    ev_flops = cm * CMUL + ca * CADD
+    ge_us = solve_ms / launches * 1e3
+    ev_us = eval_ms / launches * 1e3
+    if ge_us >= ev_us:
+        dom, dom_flops, dom_us = "elimination (k_ge)", ge_flops, ge_us
+    else:
+        dom, dom_flops, dom_us = "evaluation (k_eval)", ev_flops, ev_us
+    achieved = dom_flops / (dom_us * 1e-6) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": args.steps / el,
+        "unit": "Newton steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "n=64 sparse system, 64 monomials per polynomial, exponents uniform in {0..4}, "
+                        "unit-circle coefficients, seed 2, complex double double, total-degree homotopy at t=0.5, "
+                        f"one path, {'FULL double-double elimination' if mode == 0 else 'FP64 LU + DD refinement'}",
+            "n": n, "monomials_per_polynomial": cfg.m, "max_exponent": cfg.E, "limbs": L, "solve": args.mode,
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": dom,
+            "achieved": achieved,
+            "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP64_PEAK_TFLOPS,
+            "traffic": None,
+            "algorithmic_flops_per_launch": dom_flops,
+            "avg_launch_us": dom_us,
+        },
+        "kernels": {"eval_us": ev_us, "solve_us": ge_us, "eval_flops": ev_flops, "solve_flops": ge_flops,
+                    "timed_launches": launches},
+        "warmup_info": {k: info_w[k] for k in ("iterations", "residual_last")},
+    }
+    if not args.no_paths:
+        try:
+            out["paths"] = [track_case(q, "n8_dd", 2), track_case(q, "n32_dd", 2)]
+        except Exception as e:  # report, never hide, a failing path
+            out["paths"] = [{"error": str(e)}]
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sysm, x0, t)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

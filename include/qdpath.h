@@ -1,0 +1,227 @@
+/* qdpath: Newton corrector and path tracker for polynomial homotopies in
+ * double-double and quad-double complex arithmetic on AMD Instinct MI355X
+ * (gfx950).
+ *
+ * The operations follow Verschelde & Yoffe, "Quality Up in Polynomial
+ * Homotopy Continuation by Multithreaded Path Tracking" (2011):
+ *   - path tracking (Algorithm 3.1): given h(x,t) = 0 and a start solution z
+ *     at t = 0, return z with h(z,1) = 0, or fail;
+ *   - Newton's method (Algorithm 4.1): given h, z, epsilon and Max_It,
+ *     return z with ||h(z,t)|| < epsilon, or fail;
+ *   - evaluation (Section 4, array Y; Section 6): every polynomial value and
+ *     every partial derivative at a point.
+ *
+ * Conventions for every call:
+ *   - A complex multiword number is stored as [2][L] doubles: the L limbs of
+ *     the real part, largest first, then the L limbs of the imaginary part;
+ *     its value is the exact sum of the limbs.  L = 1 (double), 2 (double
+ *     double), 4 (quad double): the qdp_prec value IS L.
+ *   - Arrays are row-major with the complex number innermost.
+ *   - Functions without the _dev suffix take host pointers and return after
+ *     the GPU work finished.  _dev functions take device pointers (HIP device
+ *     memory, e.g. torch.Tensor.data_ptr() of a CUDA/HIP tensor) and only
+ *     enqueue work on hip_stream (NULL = the default stream).
+ *   - The caller owns every buffer passed in; handles own their device data.
+ *   - Every function returns a qdp_status; no exception crosses the ABI.
+ *     qdp_last_error() returns the message of the last failure on the calling
+ *     thread.  Numerical failure (Newton not converging, a zero pivot, a path
+ *     that stops before t = 1) is NOT an error status: it is reported in the
+ *     info / stats structs with QDP_OK, as the paper's "or fail" outputs.
+ *   - A handle's device workspace is shared by all calls on that handle:
+ *     calls on one handle from different streams must be ordered by the
+ *     caller; different handles are independent.
+ */
+#ifndef QDPATH_H
+#define QDPATH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { QDP_F64 = 1, QDP_DD = 2, QDP_QD = 4 } qdp_prec;
+
+typedef enum {
+  QDP_OK = 0,
+  QDP_EINVAL = 1,      /* bad argument: size, pointer, precision, exponent range */
+  QDP_ENOMEM = 2,      /* device allocation failed */
+  QDP_EDEVICE = 3,     /* a HIP runtime error */
+  QDP_ENONFINITE = 4,  /* NaN or Inf in an input */
+  QDP_EUNSUPPORTED = 5 /* a valid request this build does not implement */
+} qdp_status;
+
+typedef enum { QDP_SOLVE_FULL = 0, QDP_SOLVE_MIXED_IR = 1 } qdp_solve;
+typedef enum { QDP_PRED_SECANT = 0, QDP_PRED_LEARNED = 1, QDP_PRED_QUADRATIC = 2 } qdp_pred;
+
+typedef struct qdp_system qdp_system;
+typedef struct qdp_homotopy qdp_homotopy;
+
+/* Upload a sparse system f of n polynomials in n variables (Section 6: each
+ * polynomial is a sum of normalized monomials c x^a).
+ *   n            : 1 <= n <= 256 (quad double: n <= 128)
+ *   poly_offsets : [n+1] int32, poly_offsets[0] = 0, nondecreasing; the terms of
+ *                  polynomial i are poly_offsets[i] .. poly_offsets[i+1]-1
+ *   exps         : [terms][n] uint8 exponents (0 = variable absent)
+ *   coefs        : [terms][2][prec] doubles
+ *   prec         : limbs stored; the system can later be evaluated at this or
+ *                  any lower precision (limbs are truncated), never higher
+ * Errors: QDP_EINVAL (sizes, offsets, a polynomial without terms, the power
+ * table n*(max exponent+1) beyond the LDS budget), QDP_ENONFINITE (a
+ * coefficient limb), QDP_ENOMEM / QDP_EDEVICE. */
+qdp_status qdp_system_create(int32_t n, const int32_t *poly_offsets, const uint8_t *exps,
+                             const double *coefs, qdp_prec prec, qdp_system **out);
+void qdp_system_destroy(qdp_system *f);
+
+/* The total-degree homotopy h(x,t) = t f(x) + (1-t) gamma g(x) with
+ * g_i = x_i^(d_i) - 1, d_i the total degree of f_i (the paper writes only
+ * h(x,t); this is the homotopy of the path-tracking workloads).
+ *   gamma : [2][prec of f] doubles; the homotopy keeps a reference to f. */
+qdp_status qdp_homotopy_create(const qdp_system *f, const double *gamma, qdp_homotopy **out);
+void qdp_homotopy_destroy(qdp_homotopy *h);
+
+/* Evaluate f and its Jacobian at x (Section 4, array Y).
+ *   x   : [n][2][prec]
+ *   y   : [n][2][prec] out, y[i] = f_i(x)
+ *   jac : [n][n][2][prec] out, jac[i][v] = d f_i / d x_v
+ * prec must not exceed the system's stored precision. */
+qdp_status qdp_eval_jacobian(const qdp_system *f, const double *x, qdp_prec prec, double *y, double *jac,
+                             void *hip_stream);
+qdp_status qdp_eval_jacobian_dev(const qdp_system *f, const double *x, qdp_prec prec, double *y, double *jac,
+                                 void *hip_stream);
+
+/* Evaluate h(x,t), its Jacobian in x, and the componentwise scale
+ *   scale[i] = |t| sum_j |c_ij x^a_ij| + |(1-t) gamma| (|x_i|^(d_i) + 1)   (FP64, nullable). */
+qdp_status qdp_eval_homotopy(const qdp_homotopy *h, double t, const double *x, qdp_prec prec, double *y,
+                             double *jac, double *scale, void *hip_stream);
+qdp_status qdp_eval_homotopy_dev(const qdp_homotopy *h, double t, const double *x, qdp_prec prec, double *y,
+                                 double *jac, double *scale, void *hip_stream);
+
+typedef struct {
+  int32_t iterations;   /* Newton iterations run */
+  int32_t success;      /* residual < eps at exit (Algorithm 4.1: fail := residual >= eps) */
+  int32_t singular;     /* a zero pivot stopped the elimination */
+  int32_t nonfinite;    /* NaN/Inf met in the residual */
+  double residual_first;/* residual at the input point */
+  double residual_last; /* residual at the last evaluated point (before its update) */
+  double cond_est;      /* max/min pivot magnitude of the last elimination */
+  double dz_norm;       /* ||dz||_inf (leading limbs) of the last correction */
+  double refine_err;    /* MIXED_IR: relative size of the last refinement correction */
+  int32_t refine_steps; /* MIXED_IR: refinements in the last solve */
+  int32_t pad;
+} qdp_newton_info;
+
+/* Newton's method at fixed t (Algorithm 4.1): residual initialised to 1;
+ * while residual > eps and iterations < max_it: evaluate h and J at x,
+ * residual := max_i |h_i|_1 / max_i scale_i, solve J dx = -h by Gaussian
+ * elimination with partial pivoting, x := x + dx.  The residual uses
+ * |Re| + |Im| of the leading limbs.
+ *   x    : [n][2][prec] in/out
+ *   mode : QDP_SOLVE_FULL eliminates in working precision; QDP_SOLVE_MIXED_IR
+ *          factors an FP64 copy of J and refines the correction against the
+ *          working-precision residual (double double only).
+ * info may be NULL.  max_it >= 0; eps >= 0. */
+qdp_status qdp_newton_step(const qdp_homotopy *h, double t, double *x, qdp_prec prec, qdp_solve mode,
+                           double eps, int32_t max_it, qdp_newton_info *info, void *hip_stream);
+/* Same with x in device memory; asynchronous; read info with qdp_homotopy_last_info. */
+qdp_status qdp_newton_step_dev(const qdp_homotopy *h, double t, double *x, qdp_prec prec, qdp_solve mode,
+                               double eps, int32_t max_it, void *hip_stream);
+/* Synchronise hip_stream and return the info of the last Newton call on h at precision prec. */
+qdp_status qdp_homotopy_last_info(const qdp_homotopy *h, qdp_prec prec, qdp_newton_info *info, void *hip_stream);
+
+typedef struct qdp_policy qdp_policy;
+
+typedef struct {
+  double lambda0;       /* initial step size */
+  double lambda_min;    /* stop when the step size falls below this */
+  double lambda_max;    /* largest step size */
+  double shrink;        /* step factor after a failed correction (step back) */
+  double expand;        /* step factor after expand_after consecutive successes */
+  int32_t expand_after;
+  int32_t max_it_path;  /* Newton iterations per correction along the path */
+  double eps_path;      /* Newton residual tolerance along the path */
+  double eps_end;       /* residual tolerance of the end refinement at t = 1 (0: 64 * 2^(-53 L)) */
+  int32_t max_it_end;   /* Newton iterations of the end refinement */
+  int32_t predictor;    /* qdp_pred */
+  int64_t max_steps;    /* stop after this many corrections */
+  int32_t mode;         /* qdp_solve */
+  int32_t pad;
+  const qdp_policy *policy; /* learned step control (QDP_PRED_LEARNED), else NULL */
+} qdp_track_params;
+
+typedef struct {
+  int32_t fail;              /* stopped with t < 1 */
+  int32_t end_success;       /* the end refinement met eps_end */
+  double t_final;
+  int64_t succ_corrections;  /* accepted corrector stages */
+  int64_t corrections;       /* all corrector stages */
+  int64_t newton_iterations;
+  double avg_step;           /* mean accepted step size */
+  double min_step;           /* smallest accepted step size */
+  double seconds;            /* wall time of the call */
+  double end_residual;       /* residual of the last end-refinement iteration */
+  int64_t policy_used;       /* steps whose size came from the learned policy */
+  int64_t policy_rejected;   /* learned proposals the Newton test rejected */
+} qdp_track_stats;
+
+/* Fill p with the default step-size control (lambda0 0.01, halving on failure,
+ * doubling after 3 successes up to 0.08, lambda_min 0.01*2^-30, eps_path 1e-10,
+ * 4 Newton iterations per correction, 10 at the end, secant predictor, full
+ * working-precision solve). */
+qdp_status qdp_track_params_default(qdp_track_params *p);
+
+/* One step record written by qdp_track_path when step_log is not NULL. */
+typedef struct {
+  double t;          /* t before the step */
+  double lambda;     /* step size tried */
+  double rho_first;  /* Newton residual at the predicted point */
+  double rho_last;   /* last Newton residual */
+  double dz_first;   /* not used (0) */
+  double cond_est;
+  double znorm;      /* ||z||_inf before the step */
+  double pred_dist;  /* ||z_pred - z||_inf */
+  double corr_dist;  /* ||z_corrected - z_pred||_inf (accepted steps) */
+  int32_t iterations;
+  int32_t accepted;
+} qdp_step_record;
+
+/* Track one path from t = 0 to t = 1 (Algorithm 3.1): predict (secant
+ * predictor: linear extrapolation through the last two accepted points,
+ * constant before the second one), correct with Newton at the new t, control
+ * the step size (step back and shrink on failure, expand after successes),
+ * stop when the step is below lambda_min or after max_steps corrections; at
+ * t = 1 refine the endpoint.  fail = (t < 1 at exit).
+ *   x        : [n][2][prec] in: start solution at t = 0; out: end point
+ *   step_log : NULL, or room for log_cap records; the number written is
+ *              min(log_cap, corrections) */
+qdp_status qdp_track_path(const qdp_homotopy *h, double *x, qdp_prec prec, const qdp_track_params *p,
+                          qdp_track_stats *st, qdp_step_record *step_log, int64_t log_cap, void *hip_stream);
+
+/* Multiword arithmetic test entry: out[i] = op(a[i], b[i], c[i]) for
+ * count elements on the GPU (device pointers, asynchronous).  Real ops take
+ * [L] doubles per element, complex ops [2][L].
+ * op: 0 add, 1 sub, 2 mul, 3 div (real); 10 cadd, 11 csub, 12 cmul, 13 cdiv,
+ *     14 cfms (a - b*c), 15 cinv (1/a). */
+qdp_status qdp_arith_batch(int32_t op, qdp_prec prec, int64_t count, const double *a, const double *b,
+                           const double *c, double *out, void *hip_stream);
+
+/* Kernel timing with HIP events on the call's stream.  After
+ * qdp_set_timing(1) (process-wide), every Newton iteration enqueued by
+ * qdp_newton_step / _dev records an event before the evaluation kernel,
+ * between it and the elimination kernel, and after the elimination.
+ * qdp_homotopy_last_timing synchronises hip_stream and returns, for the last
+ * Newton call on h at precision prec, the summed milliseconds of all
+ * evaluation launches and of all elimination launches, and the number of
+ * iterations timed (launches of each). */
+qdp_status qdp_set_timing(int32_t on);
+qdp_status qdp_homotopy_last_timing(const qdp_homotopy *h, qdp_prec prec, double *eval_ms, double *solve_ms,
+                                    int32_t *launches, void *hip_stream);
+
+const char *qdp_last_error(void);
+const char *qdp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QDPATH_H */

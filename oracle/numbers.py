@@ -156,7 +156,10 @@ def to_limbs_real(x, L: int) -> list:
 def to_limbs_complex(z, L: int) -> np.ndarray:
     if isinstance(z, QC):
         return np.array([to_limbs_real(z.re, L), to_limbs_real(z.im, L)])
-    z = mpmath.mpc(z)
+    if isinstance(z, (int, float, complex)):
+        z = complex(z)
+        return np.array([to_limbs_real(mpmath.mpf(z.real), L), to_limbs_real(mpmath.mpf(z.imag), L)])
+    # an mpc keeps its own precision: take its parts without re-rounding
     return np.array([to_limbs_real(z.real, L), to_limbs_real(z.imag, L)])
 
 

@@ -1,0 +1,33 @@
+"""qdpath: Newton corrector and path tracker for polynomial homotopies in
+double-double / quad-double complex arithmetic, as HIP kernels for MI355X
+(gfx950) behind the C-ABI in ``include/qdpath.h``.
+
+The Python layer only marshals arguments (``binding``); the compute path is
+``libqdpath.so``.
+"""
+
+from .binding import (  # noqa: F401
+    PRED_LEARNED,
+    PRED_QUADRATIC,
+    PRED_SECANT,
+    QDP_DD,
+    QDP_F64,
+    QDP_QD,
+    SOLVE_FULL,
+    SOLVE_MIXED_IR,
+    Homotopy,
+    QdpError,
+    System,
+    arith_batch,
+    default_track_params,
+    eval_homotopy,
+    eval_homotopy_dev,
+    eval_jacobian,
+    eval_jacobian_dev,
+    last_info,
+    lib,
+    newton_step,
+    newton_step_dev,
+    track_path,
+    version,
+)

@@ -1,0 +1,344 @@
+"""ctypes binding of libqdpath.so (argument marshalling only).
+
+Every computation runs in the HIP kernels behind the C-ABI declared in
+``include/qdpath.h``; this module converts numpy arrays and torch tensors to
+pointers, checks status codes and raises ``QdpError`` with the library's
+message.  If the shared library is missing the import fails loudly: there is
+no fallback implementation.
+"""
+
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqdpath.so")
+
+QDP_F64, QDP_DD, QDP_QD = 1, 2, 4
+SOLVE_FULL, SOLVE_MIXED_IR = 0, 1
+PRED_SECANT, PRED_LEARNED, PRED_QUADRATIC = 0, 1, 2
+STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENONFINITE", 5: "EUNSUPPORTED"}
+
+ARITH_OPS = {"add": 0, "sub": 1, "mul": 2, "div": 3, "cadd": 10, "csub": 11, "cmul": 12, "cdiv": 13, "cfms": 14,
+             "cinv": 15}
+
+
+class QdpError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"qdpath {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class NewtonInfo(ct.Structure):
+    _fields_ = [
+        ("iterations", ct.c_int32),
+        ("success", ct.c_int32),
+        ("singular", ct.c_int32),
+        ("nonfinite", ct.c_int32),
+        ("residual_first", ct.c_double),
+        ("residual_last", ct.c_double),
+        ("cond_est", ct.c_double),
+        ("dz_norm", ct.c_double),
+        ("refine_err", ct.c_double),
+        ("refine_steps", ct.c_int32),
+        ("pad", ct.c_int32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
+class TrackParams(ct.Structure):
+    _fields_ = [
+        ("lambda0", ct.c_double),
+        ("lambda_min", ct.c_double),
+        ("lambda_max", ct.c_double),
+        ("shrink", ct.c_double),
+        ("expand", ct.c_double),
+        ("expand_after", ct.c_int32),
+        ("max_it_path", ct.c_int32),
+        ("eps_path", ct.c_double),
+        ("eps_end", ct.c_double),
+        ("max_it_end", ct.c_int32),
+        ("predictor", ct.c_int32),
+        ("max_steps", ct.c_int64),
+        ("mode", ct.c_int32),
+        ("pad", ct.c_int32),
+        ("policy", ct.c_void_p),
+    ]
+
+
+class TrackStats(ct.Structure):
+    _fields_ = [
+        ("fail", ct.c_int32),
+        ("end_success", ct.c_int32),
+        ("t_final", ct.c_double),
+        ("succ_corrections", ct.c_int64),
+        ("corrections", ct.c_int64),
+        ("newton_iterations", ct.c_int64),
+        ("avg_step", ct.c_double),
+        ("min_step", ct.c_double),
+        ("seconds", ct.c_double),
+        ("end_residual", ct.c_double),
+        ("policy_used", ct.c_int64),
+        ("policy_rejected", ct.c_int64),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class StepRecord(ct.Structure):
+    _fields_ = [
+        ("t", ct.c_double),
+        ("lam", ct.c_double),
+        ("rho_first", ct.c_double),
+        ("rho_last", ct.c_double),
+        ("dz_first", ct.c_double),
+        ("cond_est", ct.c_double),
+        ("znorm", ct.c_double),
+        ("pred_dist", ct.c_double),
+        ("corr_dist", ct.c_double),
+        ("iterations", ct.c_int32),
+        ("accepted", ct.c_int32),
+    ]
+
+
+_P = ct.c_void_p
+_D = ct.POINTER(ct.c_double)
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "qdp_system_create": (ct.c_int, [ct.c_int32, _P, _P, _P, ct.c_int, ct.POINTER(_P)]),
+    "qdp_system_destroy": (None, [_P]),
+    "qdp_homotopy_create": (ct.c_int, [_P, _P, ct.POINTER(_P)]),
+    "qdp_homotopy_destroy": (None, [_P]),
+    "qdp_eval_jacobian": (ct.c_int, [_P, _P, ct.c_int, _P, _P, _P]),
+    "qdp_eval_jacobian_dev": (ct.c_int, [_P, _P, ct.c_int, _P, _P, _P]),
+    "qdp_eval_homotopy": (ct.c_int, [_P, ct.c_double, _P, ct.c_int, _P, _P, _P, _P]),
+    "qdp_eval_homotopy_dev": (ct.c_int, [_P, ct.c_double, _P, ct.c_int, _P, _P, _P, _P]),
+    "qdp_newton_step": (ct.c_int, [_P, ct.c_double, _P, ct.c_int, ct.c_int, ct.c_double, ct.c_int32,
+                                   ct.POINTER(NewtonInfo), _P]),
+    "qdp_newton_step_dev": (ct.c_int, [_P, ct.c_double, _P, ct.c_int, ct.c_int, ct.c_double, ct.c_int32, _P]),
+    "qdp_homotopy_last_info": (ct.c_int, [_P, ct.c_int, ct.POINTER(NewtonInfo), _P]),
+    "qdp_track_params_default": (ct.c_int, [ct.POINTER(TrackParams)]),
+    "qdp_track_path": (ct.c_int, [_P, _P, ct.c_int, ct.POINTER(TrackParams), ct.POINTER(TrackStats),
+                                  ct.POINTER(StepRecord), ct.c_int64, _P]),
+    "qdp_arith_batch": (ct.c_int, [ct.c_int32, ct.c_int, ct.c_int64, _P, _P, _P, _P, _P]),
+    "qdp_set_timing": (ct.c_int, [ct.c_int32]),
+    "qdp_homotopy_last_timing": (ct.c_int, [_P, ct.c_int, _D, _D, ct.POINTER(ct.c_int32), _P]),
+    "qdp_last_error": (ct.c_char_p, []),
+    "qdp_version": (ct.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libqdpath.so once; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} not built: run python -m paper_1109_0545_amd.build")
+        L = ct.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise QdpError(status, lib().qdp_last_error().decode())
+
+
+def _ptr(a) -> int:
+    """Address of a contiguous numpy array or torch tensor."""
+    if isinstance(a, np.ndarray):
+        assert a.flags["C_CONTIGUOUS"], "array must be C-contiguous"
+        return a.ctypes.data
+    if a is None:
+        return None
+    assert a.is_contiguous(), "tensor must be contiguous"
+    return a.data_ptr()
+
+
+def _stream(s) -> Optional[int]:
+    if s is None:
+        return None
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+# ------------------------------------------------------------------ handles
+
+
+class System:
+    """Device copy of a sparse system (``qdp_system``)."""
+
+    def __init__(self, n: int, poly_offsets, exps, coefs, prec: int):
+        self.n = int(n)
+        self.prec = int(prec)
+        self._off = np.ascontiguousarray(poly_offsets, dtype=np.int32)
+        self._exps = np.ascontiguousarray(exps, dtype=np.uint8)
+        self._coefs = np.ascontiguousarray(coefs, dtype=np.float64)
+        if self._coefs.shape[-1] != self.prec:
+            raise ValueError("coefs must be [terms][2][prec]")
+        h = _P()
+        _check(lib().qdp_system_create(self.n, _ptr(self._off), _ptr(self._exps), _ptr(self._coefs), self.prec,
+                                       ct.byref(h)))
+        self.handle = h
+
+    @classmethod
+    def from_synth(cls, s, prec: Optional[int] = None):
+        prec = prec or s.L
+        coefs = np.ascontiguousarray(s.coefs[:, :, :prec])
+        return cls(s.n, s.poly_offsets, s.exps, coefs, prec)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().qdp_system_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Homotopy:
+    """Total-degree homotopy t f + (1-t) gamma (x^d - 1) (``qdp_homotopy``)."""
+
+    def __init__(self, system: System, gamma):
+        self.system = system
+        g = np.ascontiguousarray(np.asarray(gamma, dtype=np.float64)[:, : system.prec])
+        h = _P()
+        _check(lib().qdp_homotopy_create(system.handle, _ptr(g), ct.byref(h)))
+        self.handle = h
+        self.n = system.n
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().qdp_homotopy_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ calls
+
+
+def eval_jacobian(system: System, x: np.ndarray, prec: int, stream=None) -> Tuple[np.ndarray, np.ndarray]:
+    n = system.n
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    assert x.shape == (n, 2, prec)
+    y = np.zeros((n, 2, prec))
+    J = np.zeros((n, n, 2, prec))
+    _check(lib().qdp_eval_jacobian(system.handle, _ptr(x), prec, _ptr(y), _ptr(J), _stream(stream)))
+    return y, J
+
+
+def eval_jacobian_dev(system: System, x, prec: int, y, jac, stream=None) -> None:
+    _check(lib().qdp_eval_jacobian_dev(system.handle, _ptr(x), prec, _ptr(y), _ptr(jac), _stream(stream)))
+
+
+def eval_homotopy(h: Homotopy, t: float, x: np.ndarray, prec: int, stream=None):
+    n = h.n
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    assert x.shape == (n, 2, prec)
+    y = np.zeros((n, 2, prec))
+    J = np.zeros((n, n, 2, prec))
+    S = np.zeros(n)
+    _check(lib().qdp_eval_homotopy(h.handle, float(t), _ptr(x), prec, _ptr(y), _ptr(J), _ptr(S), _stream(stream)))
+    return y, J, S
+
+
+def eval_homotopy_dev(h: Homotopy, t: float, x, prec: int, y, jac, scale=None, stream=None) -> None:
+    _check(lib().qdp_eval_homotopy_dev(h.handle, float(t), _ptr(x), prec, _ptr(y), _ptr(jac), _ptr(scale),
+                                       _stream(stream)))
+
+
+def newton_step(h: Homotopy, t: float, x: np.ndarray, prec: int, mode: int = SOLVE_FULL, eps: float = 1e-10,
+                max_it: int = 4, stream=None):
+    """Returns (new x, info dict)."""
+    x = np.array(x, dtype=np.float64, copy=True, order="C")
+    assert x.shape == (h.n, 2, prec)
+    info = NewtonInfo()
+    _check(lib().qdp_newton_step(h.handle, float(t), _ptr(x), prec, mode, float(eps), int(max_it), ct.byref(info),
+                                 _stream(stream)))
+    return x, info.as_dict()
+
+
+def newton_step_dev(h: Homotopy, t: float, x, prec: int, mode: int = SOLVE_FULL, eps: float = 1e-10,
+                    max_it: int = 4, stream=None) -> None:
+    _check(lib().qdp_newton_step_dev(h.handle, float(t), _ptr(x), prec, mode, float(eps), int(max_it),
+                                     _stream(stream)))
+
+
+def last_info(h: Homotopy, prec: int, stream=None) -> dict:
+    info = NewtonInfo()
+    _check(lib().qdp_homotopy_last_info(h.handle, prec, ct.byref(info), _stream(stream)))
+    return info.as_dict()
+
+
+def default_track_params(**overrides) -> TrackParams:
+    p = TrackParams()
+    _check(lib().qdp_track_params_default(ct.byref(p)))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def track_path(h: Homotopy, x0: np.ndarray, prec: int, params: Optional[TrackParams] = None, log_cap: int = 0,
+               stream=None):
+    """Returns (endpoint, stats dict, step log list or None)."""
+    x = np.array(x0, dtype=np.float64, copy=True, order="C")
+    assert x.shape == (h.n, 2, prec)
+    st = TrackStats()
+    p = params if params is not None else default_track_params()
+    log = (StepRecord * log_cap)() if log_cap > 0 else None
+    _check(lib().qdp_track_path(h.handle, _ptr(x), prec, ct.byref(p), ct.byref(st), log, int(log_cap),
+                                _stream(stream)))
+    recs = None
+    if log is not None:
+        k = min(log_cap, st.corrections)
+        recs = [{f: getattr(log[i], f) for f, _ in StepRecord._fields_} for i in range(k)]
+    return x, st.as_dict(), recs
+
+
+def arith_batch(op: str, prec: int, a, b=None, c=None, stream=None):
+    """Elementwise multiword op on device tensors (float64, [count][L] or [count][2][L])."""
+    import torch
+
+    out = torch.empty_like(a)
+    count = a.shape[0]
+    _check(lib().qdp_arith_batch(ARITH_OPS[op], prec, count, _ptr(a), _ptr(b), _ptr(c), _ptr(out),
+                                 _stream(stream)))
+    return out
+
+
+def set_timing(on: bool) -> None:
+    _check(lib().qdp_set_timing(1 if on else 0))
+
+
+def last_timing(h: Homotopy, prec: int, stream=None):
+    """(eval ms summed, solve ms summed, iterations timed) of the last Newton call."""
+    a, b, k = ct.c_double(), ct.c_double(), ct.c_int32()
+    _check(lib().qdp_homotopy_last_timing(h.handle, prec, ct.byref(a), ct.byref(b), ct.byref(k), _stream(stream)))
+    return a.value, b.value, k.value
+
+
+def version() -> str:
+    return lib().qdp_version().decode()

@@ -1,0 +1,630 @@
+// C-ABI of the HIP path: handles, validation, device workspace, the Newton
+// loop of Algorithm 4.1 as a fixed sequence of gated kernels, and the path
+// tracker of Algorithm 3.1.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/qdpath.h"
+#include "common.hpp"
+
+namespace qdp {
+hipError_t launch_ge_scaled(int L, int n, double *ab, double *scale, double *x, double *dz, NewtonState *st,
+                            hipStream_t s);
+hipError_t launch_arith(int op, int L, int64_t count, const double *a, const double *b, const double *c,
+                        double *out, hipStream_t s);
+hipError_t launch_init_state(NewtonState *st, double eps, int max_it, hipStream_t s);
+hipError_t launch_predict(int L, int n, const double *x, const double *xprev, double r, int have_prev,
+                          double *xpred, hipStream_t s);
+hipError_t launch_copy(double *dst, const double *src, size_t count, hipStream_t s);
+hipError_t launch_mixed_solve(int n, double *ab, double *scale, double *x, NewtonState *st, double *lu,
+                              double *work, int refinements, hipStream_t s);
+}  // namespace qdp
+
+using qdp::DevSystem;
+using qdp::NewtonState;
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_err;
+static const bool kMixedBuilt = false;
+static int g_timing = 0;
+
+static qdp_status fail(qdp_status s, const std::string &msg) {
+  g_err = msg;
+  return s;
+}
+#define HIPCHK(expr)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(QDP_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_));          \
+  } while (0)
+
+extern "C" const char *qdp_last_error(void) { return g_err.c_str(); }
+extern "C" const char *qdp_version(void) { return "qdpath 0.1 (gfx950)"; }
+
+static bool valid_prec(int p) { return p == 1 || p == 2 || p == 4; }
+
+// ------------------------------------------------------------------ handles
+
+struct qdp_system {
+  int n = 0, L = 0, terms = 0, emax = 0, maxm = 0, npad = 0;
+  std::vector<int32_t> deg;
+  int32_t *d_offsets = nullptr, *d_deg = nullptr;
+  uint8_t *d_exps = nullptr;
+  double *d_coefs = nullptr;
+  DevSystem dev() const {
+    return DevSystem{n, terms, L, npad, emax, maxm, d_offsets, d_exps, d_coefs, d_deg};
+  }
+};
+
+struct Workspace {
+  int L = 0;
+  double *ab = nullptr;     // (n+1) x n column-major [A | -h]
+  double *scale = nullptr;  // [n]
+  double *x = nullptr;      // [n] point (compute precision)
+  double *xprev = nullptr;  // [n] previous accepted point
+  double *xw = nullptr;     // [n] working point (predicted / corrected)
+  double *y = nullptr;      // [n] values (eval entry points)
+  double *jac = nullptr;    // [n][n] Jacobian (eval entry points)
+  double *lu = nullptr;     // mixed precision: FP64 factors
+  double *work = nullptr;   // mixed precision scratch
+  NewtonState *st = nullptr;
+  std::vector<hipEvent_t> ev;  // timing: 3 events per iteration (before eval, between, after solve)
+  int timed_its = 0;
+};
+
+struct qdp_homotopy {
+  const qdp_system *f = nullptr;
+  double gamma[8] = {0};  // [2][L of f]
+  Workspace ws[3];        // by compute precision: L = 1, 2, 4
+  std::mutex mu;
+};
+
+static int ws_index(int L) { return L == 1 ? 0 : (L == 2 ? 1 : 2); }
+
+static qdp_status ensure_ws(qdp_homotopy *h, int L, Workspace **out) {
+  Workspace &w = h->ws[ws_index(L)];
+  const int n = h->f->n;
+  if (!w.ab) {
+    const size_t e = 2 * (size_t)L;
+    HIPCHK(hipMalloc(&w.ab, (size_t)n * (n + 1) * e * sizeof(double)));
+    HIPCHK(hipMalloc(&w.scale, (size_t)n * sizeof(double)));
+    HIPCHK(hipMalloc(&w.x, (size_t)n * e * sizeof(double)));
+    HIPCHK(hipMalloc(&w.xprev, (size_t)n * e * sizeof(double)));
+    HIPCHK(hipMalloc(&w.xw, (size_t)n * e * sizeof(double)));
+    HIPCHK(hipMalloc(&w.y, (size_t)n * e * sizeof(double)));
+    HIPCHK(hipMalloc(&w.jac, (size_t)n * n * e * sizeof(double)));
+    HIPCHK(hipMalloc(&w.st, sizeof(NewtonState)));
+    if (L == 2) {
+      HIPCHK(hipMalloc(&w.lu, (size_t)n * (n + 1) * 2 * sizeof(double)));
+      HIPCHK(hipMalloc(&w.work, (size_t)n * 8 * 2 * sizeof(double)));
+    }
+    w.L = L;
+  }
+  *out = &w;
+  return QDP_OK;
+}
+
+static void free_ws(Workspace &w) {
+  hipFree(w.ab);
+  hipFree(w.scale);
+  hipFree(w.x);
+  hipFree(w.xprev);
+  hipFree(w.xw);
+  hipFree(w.y);
+  hipFree(w.jac);
+  hipFree(w.lu);
+  hipFree(w.work);
+  hipFree(w.st);
+  for (auto &e : w.ev) hipEventDestroy(e);
+  w = Workspace();
+}
+
+static size_t table_bytes(int n, int emax, int L) { return 2 * (size_t)n * (emax + 1) * 16 * L; }
+
+extern "C" qdp_status qdp_system_create(int32_t n, const int32_t *off, const uint8_t *exps, const double *coefs,
+                                        qdp_prec prec, qdp_system **out) {
+  if (!out) return fail(QDP_EINVAL, "out is NULL");
+  *out = nullptr;
+  const int L = (int)prec;
+  if (!valid_prec(L)) return fail(QDP_EINVAL, "prec must be 1, 2 or 4");
+  if (n < 1 || n > 256) return fail(QDP_EINVAL, "n must be in [1, 256]");
+  if (L == 4 && n > 128) return fail(QDP_EINVAL, "quad double supports n <= 128");
+  if (!off || !exps || !coefs) return fail(QDP_EINVAL, "NULL input array");
+  if (off[0] != 0) return fail(QDP_EINVAL, "poly_offsets[0] must be 0");
+  int maxm = 0;
+  for (int i = 0; i < n; ++i) {
+    if (off[i + 1] <= off[i]) return fail(QDP_EINVAL, "every polynomial needs at least one term");
+    maxm = std::max(maxm, off[i + 1] - off[i]);
+  }
+  const int terms = off[n];
+  if (terms > (1 << 26)) return fail(QDP_EINVAL, "too many terms");
+  for (size_t q = 0; q < (size_t)terms * 2 * L; ++q)
+    if (!std::isfinite(coefs[q])) return fail(QDP_ENONFINITE, "non-finite coefficient limb");
+  auto *s = new qdp_system();
+  s->n = n;
+  s->L = L;
+  s->terms = terms;
+  s->maxm = maxm;
+  int np = 8;
+  while (np < n) np <<= 1;
+  s->npad = np;
+  std::vector<uint8_t> padded((size_t)terms * np, 0);
+  int emax = 0;
+  s->deg.assign(n, 0);
+  for (int i = 0; i < n; ++i)
+    for (int j = off[i]; j < off[i + 1]; ++j) {
+      int tot = 0;
+      for (int v = 0; v < n; ++v) {
+        const uint8_t e = exps[(size_t)j * n + v];
+        padded[(size_t)j * np + v] = e;
+        emax = std::max(emax, (int)e);
+        tot += e;
+      }
+      s->deg[i] = std::max(s->deg[i], tot);
+    }
+  s->emax = emax;
+  // the power tables of the evaluation kernel live in LDS; the reduction
+  // area reuses the same space
+  if (table_bytes(n, emax, L) > 150 * 1024) {
+    delete s;
+    return fail(QDP_EINVAL, "n * (max exponent + 1) too large for the LDS power table");
+  }
+  hipError_t e = hipSuccess;
+  e = hipMalloc(&s->d_offsets, (n + 1) * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc(&s->d_deg, n * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc(&s->d_exps, padded.size());
+  if (e == hipSuccess) e = hipMalloc(&s->d_coefs, (size_t)terms * 2 * L * sizeof(double));
+  if (e == hipSuccess) e = hipMemcpy(s->d_offsets, off, (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(s->d_deg, s->deg.data(), n * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(s->d_exps, padded.data(), padded.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(s->d_coefs, coefs, (size_t)terms * 2 * L * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    qdp_system_destroy(s);
+    return fail(e == hipErrorOutOfMemory ? QDP_ENOMEM : QDP_EDEVICE, hipGetErrorString(e));
+  }
+  *out = s;
+  return QDP_OK;
+}
+
+extern "C" void qdp_system_destroy(qdp_system *s) {
+  if (!s) return;
+  hipFree(s->d_offsets);
+  hipFree(s->d_deg);
+  hipFree(s->d_exps);
+  hipFree(s->d_coefs);
+  delete s;
+}
+
+extern "C" qdp_status qdp_homotopy_create(const qdp_system *f, const double *gamma, qdp_homotopy **out) {
+  if (!out || !f || !gamma) return fail(QDP_EINVAL, "NULL argument");
+  for (int k = 0; k < 2 * f->L; ++k)
+    if (!std::isfinite(gamma[k])) return fail(QDP_ENONFINITE, "non-finite gamma");
+  auto *h = new qdp_homotopy();
+  h->f = f;
+  for (int k = 0; k < 2 * f->L; ++k) h->gamma[k] = gamma[k];
+  *out = h;
+  return QDP_OK;
+}
+
+extern "C" void qdp_homotopy_destroy(qdp_homotopy *h) {
+  if (!h) return;
+  for (auto &w : h->ws) free_ws(w);
+  delete h;
+}
+
+// gamma truncated to L limbs: [re L][im L]
+static qdp::HomArgs hom_args(const qdp_homotopy *h, int L, double t, int on) {
+  qdp::HomArgs a{};
+  a.homotopy = on;
+  a.t = t;
+  const int LS = h ? h->f->L : L;
+  if (h)
+    for (int k = 0; k < L; ++k) {
+      a.gamma[k] = h->gamma[k];
+      a.gamma[L + k] = h->gamma[LS + k];
+    }
+  return a;
+}
+
+// ------------------------------------------------------------------ evaluation
+
+static qdp_status check_point(int n, int L, const double *x) {
+  for (size_t q = 0; q < (size_t)n * 2 * L; ++q)
+    if (!std::isfinite(x[q])) return fail(QDP_ENONFINITE, "non-finite point limb");
+  return QDP_OK;
+}
+
+static qdp_status eval_common(const qdp_system *f, const qdp_homotopy *h, double t, const double *x_dev, int L,
+                              double *y_dev, double *jac_dev, double *scale_dev, hipStream_t st) {
+  if (!f) return fail(QDP_EINVAL, "NULL system");
+  if (!valid_prec(L) || L > f->L) return fail(QDP_EINVAL, "prec must be 1, 2 or 4 and not above the system's");
+  if (!x_dev || !y_dev || !jac_dev) return fail(QDP_EINVAL, "NULL buffer");
+  qdp::EvalOut o{jac_dev, f->n, 1, y_dev, 1, 1.0, scale_dev};
+  HIPCHK(qdp::launch_eval(L, f->dev(), x_dev, hom_args(h, L, t, h != nullptr), o, nullptr, st));
+  return QDP_OK;
+}
+
+extern "C" qdp_status qdp_eval_jacobian_dev(const qdp_system *f, const double *x, qdp_prec prec, double *y,
+                                            double *jac, void *stream) {
+  return eval_common(f, nullptr, 1.0, x, (int)prec, y, jac, nullptr, (hipStream_t)stream);
+}
+
+extern "C" qdp_status qdp_eval_homotopy_dev(const qdp_homotopy *h, double t, const double *x, qdp_prec prec,
+                                            double *y, double *jac, double *scale, void *stream) {
+  if (!h) return fail(QDP_EINVAL, "NULL homotopy");
+  if (!std::isfinite(t)) return fail(QDP_ENONFINITE, "non-finite t");
+  return eval_common(h->f, h, t, x, (int)prec, y, jac, scale, (hipStream_t)stream);
+}
+
+static qdp_status eval_host(const qdp_system *f, const qdp_homotopy *h, double t, const double *x, int L,
+                            double *y, double *jac, double *scale, hipStream_t st) {
+  if (!f || !x || !y || !jac) return fail(QDP_EINVAL, "NULL argument");
+  if (!valid_prec(L) || L > f->L) return fail(QDP_EINVAL, "prec must be 1, 2 or 4 and not above the system's");
+  qdp_status s = check_point(f->n, L, x);
+  if (s != QDP_OK) return s;
+  const int n = f->n;
+  const size_t e = 2 * (size_t)L;
+  double *dx = nullptr, *dy = nullptr, *dj = nullptr, *ds = nullptr;
+  auto cleanup = [&]() {
+    hipFree(dx);
+    hipFree(dy);
+    hipFree(dj);
+    hipFree(ds);
+  };
+  hipError_t err = hipMalloc(&dx, n * e * sizeof(double));
+  if (err == hipSuccess) err = hipMalloc(&dy, n * e * sizeof(double));
+  if (err == hipSuccess) err = hipMalloc(&dj, (size_t)n * n * e * sizeof(double));
+  if (err == hipSuccess && scale) err = hipMalloc(&ds, n * sizeof(double));
+  if (err == hipSuccess) err = hipMemcpyAsync(dx, x, n * e * sizeof(double), hipMemcpyHostToDevice, st);
+  if (err != hipSuccess) {
+    cleanup();
+    return fail(QDP_ENOMEM, hipGetErrorString(err));
+  }
+  s = eval_common(f, h, t, dx, L, dy, dj, ds, st);
+  if (s == QDP_OK) {
+    err = hipMemcpyAsync(y, dy, n * e * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (err == hipSuccess) err = hipMemcpyAsync(jac, dj, (size_t)n * n * e * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (err == hipSuccess && scale) err = hipMemcpyAsync(scale, ds, n * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (err == hipSuccess) err = hipStreamSynchronize(st);
+    if (err != hipSuccess) s = fail(QDP_EDEVICE, hipGetErrorString(err));
+  }
+  cleanup();
+  return s;
+}
+
+extern "C" qdp_status qdp_eval_jacobian(const qdp_system *f, const double *x, qdp_prec prec, double *y,
+                                        double *jac, void *stream) {
+  return eval_host(f, nullptr, 1.0, x, (int)prec, y, jac, nullptr, (hipStream_t)stream);
+}
+
+extern "C" qdp_status qdp_eval_homotopy(const qdp_homotopy *h, double t, const double *x, qdp_prec prec,
+                                        double *y, double *jac, double *scale, void *stream) {
+  if (!h) return fail(QDP_EINVAL, "NULL homotopy");
+  if (!std::isfinite(t)) return fail(QDP_ENONFINITE, "non-finite t");
+  return eval_host(h->f, h, t, x, (int)prec, y, jac, scale, (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------------ Newton
+
+// Enqueue max_it iterations of (evaluate h and J into [A | -h], eliminate and
+// update).  Every kernel reads the device flag `active` first and returns at
+// once when the loop of Algorithm 4.1 has ended, so the host never waits
+// between iterations.
+static qdp_status enqueue_newton(qdp_homotopy *h, Workspace *w, int L, double t, double *x_dev, int mode,
+                                 double eps, int max_it, hipStream_t st) {
+  const qdp_system *f = h->f;
+  const int n = f->n;
+  HIPCHK(qdp::launch_init_state(w->st, eps, max_it, st));
+  const size_t e = 2 * (size_t)L;
+  qdp::EvalOut o{w->ab, 1, n, w->ab + (size_t)n * n * e, 1, -1.0, w->scale};
+  const qdp::HomArgs ha = hom_args(h, L, t, 1);
+  const bool timing = g_timing != 0;
+  if (timing) {
+    while (w->ev.size() < 3 * (size_t)max_it) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      w->ev.push_back(e);
+    }
+  }
+  w->timed_its = timing ? max_it : 0;
+  for (int it = 0; it < max_it; ++it) {
+    if (timing) HIPCHK(hipEventRecord(w->ev[3 * it], st));
+    HIPCHK(qdp::launch_eval(L, f->dev(), x_dev, ha, o, w->st, st));
+    if (timing) HIPCHK(hipEventRecord(w->ev[3 * it + 1], st));
+    if (mode == QDP_SOLVE_MIXED_IR)
+      HIPCHK(qdp::launch_mixed_solve(n, w->ab, w->scale, x_dev, w->st, w->lu, w->work, 3, st));
+    else
+      HIPCHK(qdp::launch_ge_scaled(L, n, w->ab, w->scale, x_dev, nullptr, w->st, st));
+    if (timing) HIPCHK(hipEventRecord(w->ev[3 * it + 2], st));
+  }
+  return QDP_OK;
+}
+
+static void info_from_state(const NewtonState &s, qdp_newton_info *info) {
+  info->iterations = s.iterations;
+  info->success = s.success;
+  info->singular = s.singular;
+  info->nonfinite = s.nonfinite;
+  info->residual_first = s.rho_first;
+  info->residual_last = s.rho;
+  info->cond_est = s.cond_est;
+  info->dz_norm = s.dz_norm;
+  info->refine_err = s.refine_err;
+  info->refine_steps = s.refine_steps;
+  info->pad = 0;
+}
+
+static qdp_status newton_checks(const qdp_homotopy *h, double t, const double *x, int L, int mode, double eps,
+                                int max_it) {
+  if (!h || !x) return fail(QDP_EINVAL, "NULL argument");
+  if (!valid_prec(L) || L > h->f->L) return fail(QDP_EINVAL, "prec must be 1, 2 or 4 and not above the system's");
+  if (!std::isfinite(t)) return fail(QDP_ENONFINITE, "non-finite t");
+  if (!(eps >= 0) || max_it < 0) return fail(QDP_EINVAL, "eps must be >= 0 and max_it >= 0");
+  if (mode != QDP_SOLVE_FULL && mode != QDP_SOLVE_MIXED_IR) return fail(QDP_EINVAL, "bad solve mode");
+  if (mode == QDP_SOLVE_MIXED_IR && (L != 2 || !kMixedBuilt))
+    return fail(QDP_EUNSUPPORTED, "mixed-precision refinement is implemented for double double");
+  return QDP_OK;
+}
+
+extern "C" qdp_status qdp_newton_step_dev(const qdp_homotopy *hc, double t, double *x, qdp_prec prec,
+                                          qdp_solve mode, double eps, int32_t max_it, void *stream) {
+  qdp_status s = newton_checks(hc, t, x, (int)prec, mode, eps, max_it);
+  if (s != QDP_OK) return s;
+  auto *h = const_cast<qdp_homotopy *>(hc);
+  std::lock_guard<std::mutex> g(h->mu);
+  Workspace *w = nullptr;
+  if ((s = ensure_ws(h, (int)prec, &w)) != QDP_OK) return s;
+  return enqueue_newton(h, w, (int)prec, t, x, mode, eps, max_it, (hipStream_t)stream);
+}
+
+extern "C" qdp_status qdp_homotopy_last_info(const qdp_homotopy *hc, qdp_prec prec, qdp_newton_info *info,
+                                             void *stream) {
+  if (!hc || !info) return fail(QDP_EINVAL, "NULL argument");
+  if (!valid_prec((int)prec)) return fail(QDP_EINVAL, "prec must be 1, 2 or 4");
+  auto *h = const_cast<qdp_homotopy *>(hc);
+  std::lock_guard<std::mutex> g(h->mu);
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  Workspace &w = h->ws[ws_index((int)prec)];
+  if (!w.st) return fail(QDP_EINVAL, "no Newton call on this homotopy at this precision yet");
+  NewtonState ns;
+  HIPCHK(hipMemcpy(&ns, w.st, sizeof(ns), hipMemcpyDeviceToHost));
+  info_from_state(ns, info);
+  return QDP_OK;
+}
+
+extern "C" qdp_status qdp_newton_step(const qdp_homotopy *hc, double t, double *x, qdp_prec prec,
+                                      qdp_solve mode, double eps, int32_t max_it, qdp_newton_info *info,
+                                      void *stream) {
+  const int L = (int)prec;
+  qdp_status s = newton_checks(hc, t, x, L, mode, eps, max_it);
+  if (s != QDP_OK) return s;
+  auto *h = const_cast<qdp_homotopy *>(hc);
+  if ((s = check_point(h->f->n, L, x)) != QDP_OK) return s;
+  std::lock_guard<std::mutex> g(h->mu);
+  Workspace *w = nullptr;
+  if ((s = ensure_ws(h, L, &w)) != QDP_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t bytes = (size_t)h->f->n * 2 * L * sizeof(double);
+  HIPCHK(hipMemcpyAsync(w->xw, x, bytes, hipMemcpyHostToDevice, st));
+  if ((s = enqueue_newton(h, w, L, t, w->xw, mode, eps, max_it, st)) != QDP_OK) return s;
+  NewtonState ns;
+  HIPCHK(hipMemcpyAsync(x, w->xw, bytes, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&ns, w->st, sizeof(ns), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (info) info_from_state(ns, info);
+  return QDP_OK;
+}
+
+extern "C" qdp_status qdp_set_timing(int32_t on) {
+  g_timing = on ? 1 : 0;
+  return QDP_OK;
+}
+
+extern "C" qdp_status qdp_homotopy_last_timing(const qdp_homotopy *hc, qdp_prec prec, double *eval_ms,
+                                               double *solve_ms, int32_t *launches, void *stream) {
+  if (!hc || !eval_ms || !solve_ms || !launches) return fail(QDP_EINVAL, "NULL argument");
+  if (!valid_prec((int)prec)) return fail(QDP_EINVAL, "prec must be 1, 2 or 4");
+  auto *h = const_cast<qdp_homotopy *>(hc);
+  std::lock_guard<std::mutex> g(h->mu);
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  Workspace &w = h->ws[ws_index((int)prec)];
+  double a = 0, b = 0;
+  int k = 0;
+  // iterations that ran gated-off still count as launches; their kernels
+  // return at once, which the caller sees as a shorter average
+  for (int it = 0; it < w.timed_its; ++it) {
+    float ea = 0, eb = 0;
+    HIPCHK(hipEventElapsedTime(&ea, w.ev[3 * it], w.ev[3 * it + 1]));
+    HIPCHK(hipEventElapsedTime(&eb, w.ev[3 * it + 1], w.ev[3 * it + 2]));
+    a += ea;
+    b += eb;
+    ++k;
+  }
+  *eval_ms = a;
+  *solve_ms = b;
+  *launches = k;
+  return QDP_OK;
+}
+
+// ------------------------------------------------------------------ tracker
+
+extern "C" qdp_status qdp_track_params_default(qdp_track_params *p) {
+  if (!p) return fail(QDP_EINVAL, "NULL params");
+  std::memset(p, 0, sizeof(*p));
+  p->lambda0 = 0.01;
+  p->lambda_min = 0.01 * std::ldexp(1.0, -30);
+  p->lambda_max = 0.08;
+  p->shrink = 0.5;
+  p->expand = 2.0;
+  p->expand_after = 3;
+  p->max_it_path = 4;
+  p->eps_path = 1e-10;
+  p->eps_end = 0.0;
+  p->max_it_end = 10;
+  p->predictor = QDP_PRED_SECANT;
+  p->max_steps = 2000000;
+  p->mode = QDP_SOLVE_FULL;
+  p->policy = nullptr;
+  return QDP_OK;
+}
+
+static double dev_norm_inf_host(const std::vector<double> &v, int n, int L) {
+  double m = 0;
+  for (int i = 0; i < n; ++i) m = std::max(m, std::fabs(v[(size_t)i * 2 * L]) + std::fabs(v[(size_t)i * 2 * L + L]));
+  return m;
+}
+
+extern "C" qdp_status qdp_track_path(const qdp_homotopy *hc, double *x, qdp_prec prec, const qdp_track_params *pp,
+                                     qdp_track_stats *stats, qdp_step_record *log, int64_t log_cap, void *stream) {
+  const int L = (int)prec;
+  if (!hc || !x || !stats) return fail(QDP_EINVAL, "NULL argument");
+  if (!valid_prec(L) || L > hc->f->L) return fail(QDP_EINVAL, "prec must be 1, 2 or 4 and not above the system's");
+  qdp_track_params p;
+  if (pp)
+    p = *pp;
+  else
+    qdp_track_params_default(&p);
+  if (!(p.lambda0 > 0) || !(p.shrink > 0 && p.shrink < 1) || !(p.expand >= 1) || p.max_it_path < 1 ||
+      p.max_it_end < 0 || !(p.lambda_max >= p.lambda0))
+    return fail(QDP_EINVAL, "bad step-size control parameters");
+  if (p.mode != QDP_SOLVE_FULL && p.mode != QDP_SOLVE_MIXED_IR) return fail(QDP_EINVAL, "bad solve mode");
+  if (p.mode == QDP_SOLVE_MIXED_IR && L != 2)
+    return fail(QDP_EUNSUPPORTED, "mixed-precision refinement is implemented for double double");
+  if (p.predictor == QDP_PRED_QUADRATIC) return fail(QDP_EUNSUPPORTED, "quadratic predictor not built");
+  if (p.predictor == QDP_PRED_LEARNED && !p.policy) return fail(QDP_EINVAL, "learned predictor needs a policy");
+  if (p.predictor == QDP_PRED_LEARNED) return fail(QDP_EUNSUPPORTED, "learned step control not built");
+  auto *h = const_cast<qdp_homotopy *>(hc);
+  const int n = h->f->n;
+  qdp_status s = check_point(n, L, x);
+  if (s != QDP_OK) return s;
+  std::lock_guard<std::mutex> g(h->mu);
+  Workspace *w = nullptr;
+  if ((s = ensure_ws(h, L, &w)) != QDP_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t cnt = (size_t)n * 2 * L;
+  const size_t bytes = cnt * sizeof(double);
+  const auto t_start = std::chrono::steady_clock::now();
+  HIPCHK(hipMemcpyAsync(w->x, x, bytes, hipMemcpyHostToDevice, st));
+
+  std::memset(stats, 0, sizeof(*stats));
+  double t = 0.0, tprev = 0.0, lam = p.lambda0;
+  bool have_prev = false, stop = false;
+  int run = 0;
+  int64_t succ = 0, corr = 0, nit = 0, nlog = 0;
+  double sum_step = 0.0, min_step = INFINITY;
+  NewtonState ns;
+  std::vector<double> hz(log ? cnt : 0), hp(log ? cnt : 0);
+  while (t < 1.0 && !stop) {
+    const double step = std::min(lam, 1.0 - t);
+    const double tn = (t + step >= 1.0) ? 1.0 : t + step;
+    const double r = have_prev ? (tn - t) / (t - tprev) : 0.0;
+    HIPCHK(qdp::launch_predict(L, n, w->x, w->xprev, r, have_prev ? 1 : 0, w->xw, st));
+    if (log) {
+      HIPCHK(hipMemcpyAsync(hz.data(), w->x, bytes, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(hp.data(), w->xw, bytes, hipMemcpyDeviceToHost, st));
+    }
+    if ((s = enqueue_newton(h, w, L, tn, w->xw, p.mode, p.eps_path, p.max_it_path, st)) != QDP_OK) return s;
+    HIPCHK(hipMemcpyAsync(&ns, w->st, sizeof(ns), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    ++corr;
+    nit += ns.iterations;
+    const bool ok = ns.success != 0;
+    if (log && nlog < log_cap) {
+      qdp_step_record &rec = log[nlog++];
+      std::memset(&rec, 0, sizeof(rec));
+      rec.t = t;
+      rec.lambda = step;
+      rec.rho_first = ns.rho_first;
+      rec.rho_last = ns.rho;
+      rec.cond_est = ns.cond_est;
+      rec.znorm = dev_norm_inf_host(hz, n, L);
+      double pd = 0;
+      for (int i = 0; i < n; ++i)
+        pd = std::max(pd, std::fabs(hp[(size_t)i * 2 * L] - hz[(size_t)i * 2 * L]) +
+                              std::fabs(hp[(size_t)i * 2 * L + L] - hz[(size_t)i * 2 * L + L]));
+      rec.pred_dist = pd;
+      rec.iterations = ns.iterations;
+      rec.accepted = ok ? 1 : 0;
+    }
+    if (ok) {
+      // accept: (x_prev, t_prev) <- (x, t); (x, t) <- (corrected, tn)
+      std::swap(w->xprev, w->x);
+      std::swap(w->x, w->xw);
+      tprev = t;
+      t = tn;
+      have_prev = true;
+      ++succ;
+      sum_step += step;
+      min_step = std::min(min_step, step);
+      if (++run >= p.expand_after) {
+        lam = std::min(lam * p.expand, p.lambda_max);
+        run = 0;
+      }
+    } else {
+      lam *= p.shrink;  // step back: keep (x, t)
+      run = 0;
+    }
+    stop = lam < p.lambda_min || corr >= p.max_steps;
+  }
+  stats->end_success = 0;
+  if (t >= 1.0) {
+    // end refinement at t = 1: Newton until eps_end, max_it_end, or the
+    // residual stops decreasing
+    const double eps_end = p.eps_end > 0 ? p.eps_end : 64.0 * std::ldexp(1.0, -53 * L);
+    double prev = INFINITY;
+    double rho = 1.0;
+    int it = 0;
+    while (rho > eps_end && it < p.max_it_end) {
+      if ((s = enqueue_newton(h, w, L, 1.0, w->x, p.mode, 0.0, 1, st)) != QDP_OK) return s;
+      HIPCHK(hipMemcpyAsync(&ns, w->st, sizeof(ns), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      rho = ns.rho;
+      ++it;
+      if (ns.singular || !(rho == rho)) break;
+      if (rho >= prev) break;
+      prev = rho;
+    }
+    nit += it;
+    stats->end_success = rho < eps_end ? 1 : 0;
+    stats->end_residual = rho;
+  }
+  HIPCHK(hipMemcpyAsync(x, w->x, bytes, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  stats->fail = t < 1.0 ? 1 : 0;
+  stats->t_final = t;
+  stats->succ_corrections = succ;
+  stats->corrections = corr;
+  stats->newton_iterations = nit;
+  stats->avg_step = succ ? sum_step / (double)succ : 0.0;
+  stats->min_step = succ ? min_step : 0.0;
+  stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  return QDP_OK;
+}
+
+// ------------------------------------------------------------------ arithmetic test entry
+
+extern "C" qdp_status qdp_arith_batch(int32_t op, qdp_prec prec, int64_t count, const double *a, const double *b,
+                                      const double *c, double *out, void *stream) {
+  const int L = (int)prec;
+  if (!valid_prec(L)) return fail(QDP_EINVAL, "prec must be 1, 2 or 4");
+  if (count < 0 || !a || !out) return fail(QDP_EINVAL, "bad arguments");
+  const bool binary = !(op == 15);
+  if (binary && !b) return fail(QDP_EINVAL, "b is NULL");
+  if (op == 14 && !c) return fail(QDP_EINVAL, "c is NULL");
+  if (!((op >= 0 && op <= 3) || (op >= 10 && op <= 15))) return fail(QDP_EINVAL, "unknown op");
+  if (count == 0) return QDP_OK;
+  HIPCHK(qdp::launch_arith(op, L, count, a, b, c, out, (hipStream_t)stream));
+  return QDP_OK;
+}

@@ -1,0 +1,26 @@
+// Elimination dispatch by precision.
+#include "common.hpp"
+
+namespace qdp {
+
+hipError_t launch_ge_f64(int, double *, double *, double *, double *, NewtonState *, hipStream_t);
+hipError_t launch_ge_dd(int, double *, double *, double *, double *, NewtonState *, hipStream_t);
+hipError_t launch_ge_qd(int, double *, double *, double *, double *, NewtonState *, hipStream_t);
+
+size_t ge_lds_bytes(int L, int n, bool in_lds) {
+  size_t d = (size_t)2 * n * 2 * L + 16;  // inverses + rhs + reduction
+  if (in_lds) d += (size_t)n * (n + 1) * 2 * L;
+  return d * sizeof(double) + 4 * (size_t)n * sizeof(int) + 64;
+}
+
+hipError_t launch_ge_scaled(int L, int n, double *ab, double *scale, double *x, double *dz, NewtonState *st,
+                            hipStream_t s) {
+  switch (L) {
+    case 1: return launch_ge_f64(n, ab, scale, x, dz, st, s);
+    case 2: return launch_ge_dd(n, ab, scale, x, dz, st, s);
+    case 4: return launch_ge_qd(n, ab, scale, x, dz, st, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace qdp

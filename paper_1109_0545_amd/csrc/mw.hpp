@@ -1,0 +1,449 @@
+// Multiword floating point on gfx950: double (L=1), double-double (L=2) and
+// quad-double (L=4) reals and complexes, built from FP64 error-free
+// transformations.
+//
+// The paper runs its path tracker in double-double and quad-double complex
+// arithmetic (Section 1, citing Dekker's technique and the quad-double
+// algorithms of Hida, Li and Bailey; Section 2 quotes the ~8x cost of double
+// doubles over doubles).  The building blocks here are the published ones:
+//   * TwoSum (Knuth): s + e = a + b exactly, 6 flops, no ordering condition;
+//   * FastTwoSum (Dekker): same with 3 flops when |a| >= |b| (or a == 0);
+//   * TwoProd with the hardware FMA: p + e = a * b exactly, 2 flops.
+// Double-double follows the "sloppy" add and the FMA-based product; the
+// complex product sums both real products exactly before one normalisation.
+// Quad-double accumulates partial products level by level (terms of order
+// u^k at level k, u = 2^-53) with TwoSum carries, keeps levels 0..3 exactly,
+// approximates level 4, and renormalises with a bottom-up then top-down
+// TwoSum pass.  Every result is accurate to a few units of 2^(-53L) relative
+// to the componentwise scale of the operation (|a|+|b| for sums, |a||b| for
+// products), which is the bound the tests check against exact rationals.
+//
+// Must be compiled with -ffp-contract=off (no silent FMA contraction).
+
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#pragma clang fp contract(off)
+
+#define MW_DEV __device__ __forceinline__
+
+namespace mw {
+
+// ---------------------------------------------------------------- EFTs
+
+MW_DEV double two_sum(double a, double b, double &e) {
+  double s = a + b;
+  double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+  return s;
+}
+
+MW_DEV double fast_two_sum(double a, double b, double &e) {
+  double s = a + b;
+  e = b - (s - a);
+  return s;
+}
+
+MW_DEV double two_prod(double a, double b, double &e) {
+  double p = a * b;
+  e = __builtin_fma(a, b, -p);
+  return p;
+}
+
+// ---------------------------------------------------------------- real types
+
+template <int L> struct R { double v[L]; };
+template <int L> struct C { R<L> re, im; };
+
+template <int L> MW_DEV R<L> rzero() {
+  R<L> r;
+#pragma unroll
+  for (int k = 0; k < L; ++k) r.v[k] = 0.0;
+  return r;
+}
+template <int L> MW_DEV R<L> rfrom(double a) {
+  R<L> r = rzero<L>();
+  r.v[0] = a;
+  return r;
+}
+template <int L> MW_DEV R<L> rneg(const R<L> &a) {
+  R<L> r;
+#pragma unroll
+  for (int k = 0; k < L; ++k) r.v[k] = -a.v[k];
+  return r;
+}
+// multiply by a power of two (exact)
+template <int L> MW_DEV R<L> rldexp(const R<L> &a, int e) {
+  R<L> r;
+#pragma unroll
+  for (int k = 0; k < L; ++k) r.v[k] = ldexp(a.v[k], e);
+  return r;
+}
+
+// ---- quad-double helpers
+
+// renormalise five level-ordered terms into four limbs
+MW_DEV void renorm5(double &x0, double &x1, double &x2, double &x3, double x4) {
+  double e;
+  // bottom-up: x0 becomes the rounded sum, the others the carried errors
+  x3 = two_sum(x3, x4, x4);
+  x2 = two_sum(x2, x3, x3);
+  x1 = two_sum(x1, x2, x2);
+  x0 = two_sum(x0, x1, x1);
+  // top-down: make consecutive limbs nonoverlapping; zeros move down
+  x1 = two_sum(x1, x2, x2);
+  x2 = two_sum(x2, x3, x3);
+  x3 = two_sum(x3, x4, e);
+  (void)e;
+}
+
+MW_DEV void renorm4(double &x0, double &x1, double &x2, double &x3) {
+  x2 = two_sum(x2, x3, x3);
+  x1 = two_sum(x1, x2, x2);
+  x0 = two_sum(x0, x1, x1);
+  x1 = two_sum(x1, x2, x2);
+  x2 = two_sum(x2, x3, x3);
+}
+
+// ---------------------------------------------------------------- add
+
+template <int L> MW_DEV R<L> radd(const R<L> &a, const R<L> &b);
+
+template <> MW_DEV R<1> radd<1>(const R<1> &a, const R<1> &b) {
+  R<1> r;
+  r.v[0] = a.v[0] + b.v[0];
+  return r;
+}
+
+// double-double sum: exact sum of the leading limbs, the trailing limbs added
+// into its error, one normalisation (error ~ u^2 (|a| + |b|))
+template <> MW_DEV R<2> radd<2>(const R<2> &a, const R<2> &b) {
+  double e;
+  double s = two_sum(a.v[0], b.v[0], e);
+  e += a.v[1] + b.v[1];
+  R<2> r;
+  r.v[0] = fast_two_sum(s, e, r.v[1]);
+  return r;
+}
+
+// quad-double sum, level by level
+template <> MW_DEV R<4> radd<4>(const R<4> &a, const R<4> &b) {
+  double e0, e1, e2, f0, f1, g0;
+  double s0 = two_sum(a.v[0], b.v[0], e0);  // e0: level 1
+  double s1 = two_sum(a.v[1], b.v[1], e1);  // e1: level 2
+  double s2 = two_sum(a.v[2], b.v[2], e2);  // e2: level 3
+  double s3 = a.v[3] + b.v[3];              // level 3 (error level 4, dropped)
+  s1 = two_sum(s1, e0, f0);                 // f0: level 2
+  s2 = two_sum(s2, e1, f1);                 // f1: level 3
+  s2 = two_sum(s2, f0, g0);                 // g0: level 3
+  s3 = s3 + (e2 + (f1 + g0));
+  renorm4(s0, s1, s2, s3);
+  R<4> r;
+  r.v[0] = s0; r.v[1] = s1; r.v[2] = s2; r.v[3] = s3;
+  return r;
+}
+
+template <int L> MW_DEV R<L> rsub(const R<L> &a, const R<L> &b) { return radd<L>(a, rneg<L>(b)); }
+
+// ---------------------------------------------------------------- mul
+
+template <int L> MW_DEV R<L> rmul(const R<L> &a, const R<L> &b);
+
+template <> MW_DEV R<1> rmul<1>(const R<1> &a, const R<1> &b) {
+  R<1> r;
+  r.v[0] = a.v[0] * b.v[0];
+  return r;
+}
+
+template <> MW_DEV R<2> rmul<2>(const R<2> &a, const R<2> &b) {
+  double e;
+  double p = two_prod(a.v[0], b.v[0], e);
+  e = __builtin_fma(a.v[0], b.v[1], e);
+  e = __builtin_fma(a.v[1], b.v[0], e);
+  R<2> r;
+  r.v[0] = fast_two_sum(p, e, r.v[1]);
+  return r;
+}
+
+template <> MW_DEV R<4> rmul<4>(const R<4> &a, const R<4> &b) {
+  const double *x = a.v, *y = b.v;
+  double q00, q01, q10, q02, q11, q20;
+  double p00 = two_prod(x[0], y[0], q00);  // level 0, error level 1
+  double p01 = two_prod(x[0], y[1], q01);  // level 1, errors level 2
+  double p10 = two_prod(x[1], y[0], q10);
+  double p02 = two_prod(x[0], y[2], q02);  // level 2, errors level 3
+  double p11 = two_prod(x[1], y[1], q11);
+  double p20 = two_prod(x[2], y[0], q20);
+  // level 1: p01 + p10 + q00
+  double r1, r2;
+  double s1 = two_sum(p01, p10, r1);
+  s1 = two_sum(s1, q00, r2);
+  // level 2: p02 + p11 + p20 + q01 + q10 + r1 + r2
+  double u1, u2, u3, u4, u5, u6;
+  double s2 = two_sum(p02, p11, u1);
+  s2 = two_sum(s2, p20, u2);
+  s2 = two_sum(s2, q01, u3);
+  s2 = two_sum(s2, q10, u4);
+  s2 = two_sum(s2, r1, u5);
+  s2 = two_sum(s2, r2, u6);
+  // level 3: plain sums (errors at level 4)
+  double s3 = ((x[0] * y[3] + x[3] * y[0]) + (x[1] * y[2] + x[2] * y[1])) +
+              ((q02 + q11) + q20) + ((u1 + u2) + (u3 + u4)) + (u5 + u6);
+  // level 4: leading level-4 products
+  double s4 = __builtin_fma(x[1], y[3], __builtin_fma(x[2], y[2], x[3] * y[1]));
+  double s0 = p00;
+  renorm5(s0, s1, s2, s3, s4);
+  R<4> r;
+  r.v[0] = s0; r.v[1] = s1; r.v[2] = s2; r.v[3] = s3;
+  return r;
+}
+
+// multiword times a double (exact small integers and powers of two included)
+template <int L> MW_DEV R<L> rmul_d(const R<L> &a, double b);
+
+template <> MW_DEV R<1> rmul_d<1>(const R<1> &a, double b) {
+  R<1> r;
+  r.v[0] = a.v[0] * b;
+  return r;
+}
+template <> MW_DEV R<2> rmul_d<2>(const R<2> &a, double b) {
+  double e;
+  double p = two_prod(a.v[0], b, e);
+  e = __builtin_fma(a.v[1], b, e);
+  R<2> r;
+  r.v[0] = fast_two_sum(p, e, r.v[1]);
+  return r;
+}
+template <> MW_DEV R<4> rmul_d<4>(const R<4> &a, double b) {
+  double q0, q1, q2;
+  double p0 = two_prod(a.v[0], b, q0);
+  double p1 = two_prod(a.v[1], b, q1);
+  double p2 = two_prod(a.v[2], b, q2);
+  double p3 = a.v[3] * b;
+  double r1, r2, r3;
+  double s1 = two_sum(p1, q0, r1);        // level 1; r1 level 2
+  double s2 = two_sum(p2, q1, r2);        // level 2; r2 level 3
+  s2 = two_sum(s2, r1, r3);               // r3 level 3
+  double s3 = p3 + (q2 + (r2 + r3));
+  double s4 = __builtin_fma(a.v[3], b, -p3);
+  double s0 = p0;
+  renorm5(s0, s1, s2, s3, s4);
+  R<4> r;
+  r.v[0] = s0; r.v[1] = s1; r.v[2] = s2; r.v[3] = s3;
+  return r;
+}
+
+// ---------------------------------------------------------------- division
+
+// long division: q_k = (remainder leading limb) / b_0, remainder -= q_k * b
+template <int L> MW_DEV R<L> rdiv(const R<L> &a, const R<L> &b) {
+  if constexpr (L == 1) {
+    R<1> r;
+    r.v[0] = a.v[0] / b.v[0];
+    return r;
+  } else {
+    double q[L + 1];
+    R<L> rem = a;
+#pragma unroll
+    for (int k = 0; k <= L; ++k) {
+      q[k] = rem.v[0] / b.v[0];
+      if (k < L) rem = rsub<L>(rem, rmul_d<L>(b, q[k]));
+    }
+    R<L> r;
+    if constexpr (L == 2) {
+      double e;
+      double s = fast_two_sum(q[0], q[1], e);
+      e += q[2];
+      r.v[0] = fast_two_sum(s, e, r.v[1]);
+    } else {
+      double x0 = q[0], x1 = q[1], x2 = q[2], x3 = q[3];
+      renorm5(x0, x1, x2, x3, q[4]);
+      r.v[0] = x0; r.v[1] = x1; r.v[2] = x2; r.v[3] = x3;
+    }
+    return r;
+  }
+}
+
+template <int L> MW_DEV double rabs_hi(const R<L> &a) { return __builtin_fabs(a.v[0]); }
+
+// ---------------------------------------------------------------- complex
+
+template <int L> MW_DEV C<L> czero() { return C<L>{rzero<L>(), rzero<L>()}; }
+template <int L> MW_DEV C<L> cone() { return C<L>{rfrom<L>(1.0), rzero<L>()}; }
+template <int L> MW_DEV C<L> cneg(const C<L> &a) { return C<L>{rneg<L>(a.re), rneg<L>(a.im)}; }
+template <int L> MW_DEV C<L> cconj(const C<L> &a) { return C<L>{a.re, rneg<L>(a.im)}; }
+template <int L> MW_DEV C<L> cadd(const C<L> &a, const C<L> &b) {
+  return C<L>{radd<L>(a.re, b.re), radd<L>(a.im, b.im)};
+}
+template <int L> MW_DEV C<L> csub(const C<L> &a, const C<L> &b) {
+  return C<L>{rsub<L>(a.re, b.re), rsub<L>(a.im, b.im)};
+}
+template <int L> MW_DEV C<L> cmul_d(const C<L> &a, double s) {
+  return C<L>{rmul_d<L>(a.re, s), rmul_d<L>(a.im, s)};
+}
+template <int L> MW_DEV C<L> cmul_r(const C<L> &a, const R<L> &s) {
+  return C<L>{rmul<L>(a.re, s), rmul<L>(a.im, s)};
+}
+
+// double-double complex product: each component sums its two exact leading
+// products with TwoSum, folds the product errors and the cross terms into the
+// tail with FMAs, then normalises once.
+MW_DEV R<2> dd_dot2(const R<2> &a, const R<2> &b, const R<2> &c, const R<2> &d, double sgn) {
+  // a*b + sgn * c*d
+  double e1, e2, t;
+  double p1 = two_prod(a.v[0], b.v[0], e1);
+  double p2 = two_prod(sgn * c.v[0], d.v[0], e2);
+  double s = two_sum(p1, p2, t);
+  t = t + (e1 + e2);
+  t = __builtin_fma(a.v[0], b.v[1], t);
+  t = __builtin_fma(a.v[1], b.v[0], t);
+  t = __builtin_fma(sgn * c.v[0], d.v[1], t);
+  t = __builtin_fma(sgn * c.v[1], d.v[0], t);
+  R<2> r;
+  r.v[0] = fast_two_sum(s, t, r.v[1]);
+  return r;
+}
+
+template <int L> MW_DEV C<L> cmul(const C<L> &a, const C<L> &b) {
+  if constexpr (L == 1) {
+    C<1> r;
+    r.re.v[0] = __builtin_fma(a.re.v[0], b.re.v[0], -(a.im.v[0] * b.im.v[0]));
+    r.im.v[0] = __builtin_fma(a.re.v[0], b.im.v[0], a.im.v[0] * b.re.v[0]);
+    return r;
+  } else if constexpr (L == 2) {
+    return C<2>{dd_dot2(a.re, b.re, a.im, b.im, -1.0), dd_dot2(a.re, b.im, a.im, b.re, 1.0)};
+  } else {
+    return C<L>{rsub<L>(rmul<L>(a.re, b.re), rmul<L>(a.im, b.im)),
+                radd<L>(rmul<L>(a.re, b.im), rmul<L>(a.im, b.re))};
+  }
+}
+
+// a - l*u
+template <int L> MW_DEV C<L> cfms(const C<L> &a, const C<L> &l, const C<L> &u) {
+  return csub<L>(a, cmul<L>(l, u));
+}
+
+// 1/a = conj(a)/|a|^2, with a power-of-two prescale against overflow
+template <int L> MW_DEV C<L> cinv(const C<L> &a) {
+  double m = fmax(__builtin_fabs(a.re.v[0]), __builtin_fabs(a.im.v[0]));
+  int ex = 0;
+  if (m > 0.0 && m < __builtin_inf()) (void)frexp(m, &ex);
+  C<L> s{rldexp<L>(a.re, -ex), rldexp<L>(a.im, -ex)};
+  R<L> d = radd<L>(rmul<L>(s.re, s.re), rmul<L>(s.im, s.im));
+  R<L> one = rfrom<L>(1.0);
+  R<L> inv = rdiv<L>(one, d);
+  C<L> r{rmul<L>(s.re, inv), rneg<L>(rmul<L>(s.im, inv))};
+  r.re = rldexp<L>(r.re, -ex);
+  r.im = rldexp<L>(r.im, -ex);
+  return r;
+}
+
+template <int L> MW_DEV C<L> cdiv(const C<L> &a, const C<L> &b) { return cmul<L>(a, cinv<L>(b)); }
+
+// |re| + |im| of the leading limbs (pivot key and residual norm)
+template <int L> MW_DEV double cabs1_hi(const C<L> &a) {
+  return __builtin_fabs(a.re.v[0]) + __builtin_fabs(a.im.v[0]);
+}
+// FP64 modulus of the leading limbs
+template <int L> MW_DEV double cabs_hi(const C<L> &a) { return hypot(a.re.v[0], a.im.v[0]); }
+
+template <int L> MW_DEV bool cfinite(const C<L> &a) {
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < L; ++k) ok = ok && __builtin_isfinite(a.re.v[k]) && __builtin_isfinite(a.im.v[k]);
+  return ok;
+}
+
+// ---------------------------------------------------------------- memory
+// A complex multiword number in memory: [re limbs (L)][im limbs (L)] doubles.
+
+template <int L> MW_DEV C<L> cload(const double *p) {
+  C<L> r;
+#pragma unroll
+  for (int k = 0; k < L; ++k) {
+    r.re.v[k] = p[k];
+    r.im.v[k] = p[L + k];
+  }
+  return r;
+}
+// load keeping only the first L of LS stored limbs (precision truncation)
+template <int L> MW_DEV C<L> cload_trunc(const double *p, int LS) {
+  C<L> r;
+#pragma unroll
+  for (int k = 0; k < L; ++k) {
+    r.re.v[k] = p[k];
+    r.im.v[k] = p[LS + k];
+  }
+  return r;
+}
+template <int L> MW_DEV void cstore(double *p, const C<L> &a) {
+#pragma unroll
+  for (int k = 0; k < L; ++k) {
+    p[k] = a.re.v[k];
+    p[L + k] = a.im.v[k];
+  }
+}
+
+// power x^e for e >= 0 by binary powering
+template <int L> MW_DEV C<L> cpow(const C<L> &x, int e) {
+  C<L> r = cone<L>();
+  C<L> b = x;
+  while (e > 0) {
+    if (e & 1) r = cmul<L>(r, b);
+    e >>= 1;
+    if (e) b = cmul<L>(b, b);
+  }
+  return r;
+}
+
+// cross-lane shuffles of a complex multiword value
+template <int L> MW_DEV C<L> cshfl(const C<L> &a, int src, int width) {
+  C<L> r;
+#pragma unroll
+  for (int k = 0; k < L; ++k) {
+    r.re.v[k] = __shfl(a.re.v[k], src, width);
+    r.im.v[k] = __shfl(a.im.v[k], src, width);
+  }
+  return r;
+}
+template <int L> MW_DEV C<L> cshfl_up(const C<L> &a, unsigned d, int width) {
+  C<L> r;
+#pragma unroll
+  for (int k = 0; k < L; ++k) {
+    r.re.v[k] = __shfl_up(a.re.v[k], d, width);
+    r.im.v[k] = __shfl_up(a.im.v[k], d, width);
+  }
+  return r;
+}
+template <int L> MW_DEV C<L> cshfl_down(const C<L> &a, unsigned d, int width) {
+  C<L> r;
+#pragma unroll
+  for (int k = 0; k < L; ++k) {
+    r.re.v[k] = __shfl_down(a.re.v[k], d, width);
+    r.im.v[k] = __shfl_down(a.im.v[k], d, width);
+  }
+  return r;
+}
+template <int L> MW_DEV C<L> cshfl_xor(const C<L> &a, int m, int width) {
+  C<L> r;
+#pragma unroll
+  for (int k = 0; k < L; ++k) {
+    r.re.v[k] = __shfl_xor(a.re.v[k], m, width);
+    r.im.v[k] = __shfl_xor(a.im.v[k], m, width);
+  }
+  return r;
+}
+
+template <int L> MW_DEV C<L> cselect(bool c, const C<L> &a, const C<L> &b) {
+  C<L> r;
+#pragma unroll
+  for (int k = 0; k < L; ++k) {
+    r.re.v[k] = c ? a.re.v[k] : b.re.v[k];
+    r.im.v[k] = c ? a.im.v[k] : b.im.v[k];
+  }
+  return r;
+}
+
+}  // namespace mw

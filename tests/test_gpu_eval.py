@@ -1,0 +1,176 @@
+"""Evaluation + Jacobian kernel vs the plain oracle, at the workload shapes
+and on edge cases.  Tolerance: |value - oracle| <= tau * componentwise scale,
+tau = 1e-30 (double double), 1e-60 (quad double), 1e-13 (double)."""
+
+import mpmath
+import numpy as np
+import pytest
+
+from oracle.evaluate import eval_homotopy as o_eval_homotopy
+from oracle.evaluate import eval_system as o_eval_system
+from synth.systems import CONFIGS, config_system, make_system, random_point
+from tests.gpu_helpers import err_over_scale, say
+from tests.oracle_helpers import build, point
+
+pytestmark = pytest.mark.gpu
+
+TAU = {1: 1e-13, 2: 1e-30, 4: 1e-60}
+
+
+def check_eval(sysm, L, x, rows=None, form="product"):
+    import paper_1109_0545_amd as q
+
+    say("eval_jacobian n", sysm.n, "L", L, "rows", rows if rows is None else len(rows))
+    S = q.System.from_synth(sysm, prec=sysm.L)
+    y, J = q.eval_jacobian(S, x, L)
+    s_eval = sysm.truncated(L) if L < sysm.L else sysm
+    ref = o_eval_system(s_eval.exps, s_eval.coefs, s_eval.poly_offsets, x, rows=rows, form=form)
+    worst = 0.0
+    for r, i in enumerate(ref.rows):
+        worst = max(worst, err_over_scale(y[i], ref.y[r], ref.S[r]))
+        for v in range(sysm.n):
+            worst = max(worst, err_over_scale(J[i, v], ref.J[r][v], ref.SJ[r][v]))
+    assert worst <= TAU[L], worst
+    return worst
+
+
+@pytest.mark.parametrize("L", [1, 2])
+def test_eval_n8_all_rows(L):
+    s = config_system(CONFIGS["n8_dd"])
+    check_eval(s, L, random_point(s.n, L, seed=3, spread=0.3))
+
+
+def test_eval_n32_dd_all_rows():
+    s = config_system(CONFIGS["n32_dd"])
+    check_eval(s, 2, random_point(s.n, 2, seed=4, spread=0.1), form="quotient")
+
+
+def test_eval_n64_qd_sampled_rows():
+    s = config_system(CONFIGS["n64_qd"])
+    check_eval(s, 4, random_point(s.n, 4, seed=5, spread=0.05), rows=[0, 17, 63], form="quotient")
+
+
+def test_eval_n64_qd_at_dd_precision_truncates():
+    s = config_system(CONFIGS["n64_qd"])
+    check_eval(s, 2, random_point(s.n, 2, seed=6, spread=0.05), rows=[1, 40], form="quotient")
+
+
+def test_eval_n128_dd_sampled_rows():
+    s = config_system(CONFIGS["n128_dd"])
+    check_eval(s, 2, random_point(s.n, 2, seed=7, spread=0.02), rows=[0, 127], form="quotient")
+
+
+@pytest.mark.parametrize("n,m,E,L,seed", [(1, 5, 6, 2, 1), (3, 7, 5, 4, 2), (5, 11, 3, 2, 3), (40, 9, 2, 2, 4),
+                                          (17, 3, 4, 4, 5), (100, 6, 2, 2, 6)])
+def test_eval_ragged_shapes(n, m, E, L, seed):
+    # n not a power of two, m not a multiple of the monomial slots per workgroup
+    s = make_system(n, m, E, L, seed)
+    rows = None if n <= 40 else [0, n // 2, n - 1]
+    check_eval(s, L, random_point(n, L, seed=seed + 10, spread=0.2), rows=rows,
+               form="product" if n <= 17 else "quotient")
+
+
+def test_eval_variable_term_counts_and_constants():
+    # polynomials with 1, 2 and 9 terms; constant monomials; a zero exponent row
+    import paper_1109_0545_amd as q
+
+    polys = [
+        [((0.5, -0.25), [0, 0, 0])],
+        [((1, 0), [3, 0, 1]), ((-2, 1), [0, 0, 0])],
+        [((k / 8, 1 - k / 8), [k % 3, (k * 2) % 4, k % 2]) for k in range(9)],
+    ]
+    from fractions import Fraction
+
+    polys = [[((Fraction(c[0]).limit_denominator(64), Fraction(c[1]).limit_denominator(64)), a) for c, a in p]
+             for p in polys]
+    exps, coefs, offs = build(polys, 3, 2)
+    from synth.systems import System
+
+    s = System(3, 2, offs, exps, coefs, np.zeros((2, 2)), np.zeros((3, 2, 2)), np.zeros(3, np.int64),
+               np.zeros(3, np.int32))
+    check_eval(s, 2, point([(Fraction(3, 4), Fraction(-1, 2)), (Fraction(5, 8), 0), (0, Fraction(7, 8))]))
+
+
+def test_speelpenning_closed_form_on_gpu():
+    # f_0 = prod_v x_v at x_v = r: every partial is r^(n-1)
+    import paper_1109_0545_amd as q
+    from fractions import Fraction
+
+    n = 48
+    polys = [[((1, 0), [1] * n)]] + [[((1, 0), [0] * n)]] * (n - 1)
+    exps, coefs, offs = build(polys, n, 2)
+    S = q.System(n, offs, exps, coefs, 2)
+    r = (Fraction(7, 8), Fraction(1, 4))
+    x = point([r] * n)
+    say("speelpenning n", n)
+    y, J = q.eval_jacobian(S, x, 2)
+    with mpmath.workprec(400):
+        rc = mpmath.mpc(mpmath.mpf(7) / 8, mpmath.mpf(1) / 4)
+        ref = rc ** (n - 1)
+        from oracle.numbers import mpc_of
+
+        for v in range(n):
+            assert abs(mpc_of(J[0, v]) - ref) <= 1e-30 * abs(ref)
+
+
+@pytest.mark.parametrize("t", [0.0, 0.37, 1.0])
+def test_eval_homotopy_n32(t):
+    import paper_1109_0545_amd as q
+
+    s = config_system(CONFIGS["n32_dd"])
+    S = q.System.from_synth(s)
+    H = q.Homotopy(S, s.gamma)
+    x = random_point(s.n, 2, seed=8, spread=0.05)
+    say("eval_homotopy n32 t", t)
+    y, J, sc = q.eval_homotopy(H, t, x, 2)
+    rows = [0, 5, 31]
+    ref = o_eval_homotopy(s.exps, s.coefs, s.poly_offsets, s.gamma, t, x, rows=rows, form="quotient")
+    for r, i in enumerate(rows):
+        assert err_over_scale(y[i], ref.y[r], ref.S[r]) <= 1e-30
+        assert abs(sc[i] - float(ref.S[r])) <= 1e-12 * float(ref.S[r])
+        for v in range(s.n):
+            assert err_over_scale(J[i, v], ref.J[r][v], ref.SJ[r][v]) <= 1e-30
+
+
+def test_eval_dev_variant_matches_host_variant():
+    import torch
+
+    import paper_1109_0545_amd as q
+
+    s = config_system(CONFIGS["n32_dd"])
+    S = q.System.from_synth(s)
+    x = random_point(s.n, 2, seed=9, spread=0.1)
+    say("eval_jacobian_dev n32")
+    y, J = q.eval_jacobian(S, x, 2)
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.zeros((s.n, 2, 2), dtype=torch.float64, device="cuda")
+    Jd = torch.zeros((s.n, s.n, 2, 2), dtype=torch.float64, device="cuda")
+    q.eval_jacobian_dev(S, xd, 2, yd, Jd, stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    assert np.array_equal(yd.cpu().numpy(), y) and np.array_equal(Jd.cpu().numpy(), J)
+
+
+def test_eval_is_deterministic():
+    import paper_1109_0545_amd as q
+
+    s = config_system(CONFIGS["n64_dd"])
+    S = q.System.from_synth(s)
+    x = random_point(s.n, 2, seed=10, spread=0.05)
+    say("eval determinism n64")
+    a = q.eval_jacobian(S, x, 2)
+    b = q.eval_jacobian(S, x, 2)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_eval_rejects_bad_precision_and_nonfinite():
+    import paper_1109_0545_amd as q
+
+    s = config_system(CONFIGS["n8_dd"])
+    S = q.System.from_synth(s)
+    with pytest.raises(q.QdpError):
+        q.eval_jacobian(S, np.zeros((8, 2, 4)), 4)  # above the stored precision
+    x = random_point(8, 2, seed=1)
+    x[3, 1, 0] = np.inf
+    with pytest.raises(q.QdpError) as e:
+        q.eval_jacobian(S, x, 2)
+    assert e.value.status == 4

@@ -1,0 +1,130 @@
+"""Newton corrector (eval + GE + back substitution + update) vs the oracle."""
+
+import mpmath
+import numpy as np
+import pytest
+
+from oracle.newton import cond_inf, newton_step as o_newton_step, newton_tolerance
+from oracle.numbers import mpc_of, to_limbs_complex
+from synth.systems import CONFIGS, config_system, start_root
+from tests.gpu_helpers import fixture, say, zss_mpc
+
+pytestmark = pytest.mark.gpu
+
+
+def limbs_point(vals, L):
+    return np.stack([to_limbs_complex(mpmath.mpc(v), L) for v in vals])
+
+
+def one_step_parity(name, L, t=0.5, form="product"):
+    import paper_1109_0545_amd as q
+
+    s = config_system(CONFIGS[name])
+    s = s.truncated(L) if L < s.L else s
+    fix = fixture(name)
+    x = limbs_point([complex(a, b) for a, b in fix["x_half_f64"]], L)
+    S = q.System.from_synth(s)
+    H = q.Homotopy(S, s.gamma)
+    say("newton one step", name, "L", L, "t", t)
+    xg, info = q.newton_step(H, t, x, L, eps=0.0, max_it=1)
+    assert info["iterations"] == 1 and not info["success"] and not info["singular"]
+    ref = o_newton_step(s.exps, s.coefs, s.poly_offsets, s.gamma, t, x, form=form)
+    with mpmath.workprec(600):
+        kappa = cond_inf(ref.J, 300)
+        dzn = max(float(abs(d)) for d in ref.dz)
+        zn = max(float(abs(z)) for z in ref.z)
+        tol = newton_tolerance(s.n, kappa, L, dzn, zn)
+        err = max(float(abs(mpc_of(xg[v]) - ref.z[v])) for v in range(s.n))
+    assert err <= tol, (err, tol, kappa)
+    # the residual agrees to FP64 unless it sits at the rounding floor of L limbs
+    assert abs(info["residual_first"] - ref.rho) <= 1e-6 * ref.rho + 64 * s.n * 2.0 ** (-53 * L)
+    return err, tol
+
+
+def test_one_step_n8_dd():
+    one_step_parity("n8_dd", 2)
+
+
+def test_one_step_n8_f64():
+    one_step_parity("n8_dd", 1)
+
+
+def test_one_step_n32_dd():
+    one_step_parity("n32_dd", 2, form="quotient")
+
+
+def test_one_step_n64_qd():
+    one_step_parity("n64_qd", 4, form="quotient")
+
+
+@pytest.mark.parametrize("name,L", [("n8_dd", 2), ("n32_dd", 2), ("n64_qd", 4), ("n64_dd", 2), ("n128_dd", 2)])
+def test_converges_to_target_root(name, L):
+    # at t = 1 (h = f) from the planted point cut to one limb, Newton reaches
+    # the exact root z** of the stored system to working precision
+    import paper_1109_0545_amd as q
+
+    fix = fixture(name)
+    s = config_system(CONFIGS[name])
+    S = q.System.from_synth(s)
+    H = q.Homotopy(S, s.gamma)
+    x = np.zeros((s.n, 2, L))
+    x[:, :, 0] = s.zstar[:, :, 0]
+    say("newton converge", name)
+    xg, info = q.newton_step(H, 1.0, x, L, eps=64 * 2.0 ** (-53 * L), max_it=6)
+    zss = zss_mpc(fix)
+    with mpmath.workprec(600):
+        err = max(float(abs(mpc_of(xg[v]) - zss[v])) for v in range(s.n))
+    assert info["success"] and 2 <= info["iterations"] <= 6
+    assert err <= 1e4 * 2.0 ** (-53 * L), err
+
+
+def test_loop_semantics_on_gpu():
+    import paper_1109_0545_amd as q
+
+    s = config_system(CONFIGS["n8_dd"])
+    S = q.System.from_synth(s)
+    H = q.Homotopy(S, s.gamma)
+    x = s.zstar.copy()
+    say("newton semantics")
+    xg, info = q.newton_step(H, 1.0, x, 2, eps=1.0, max_it=5)
+    assert info["iterations"] == 0 and not info["success"] and np.array_equal(xg, x)
+    xg, info = q.newton_step(H, 1.0, x, 2, eps=2.0, max_it=5)
+    assert info["iterations"] == 0 and info["success"]
+    xg, info = q.newton_step(H, 1.0, x, 2, eps=0.0, max_it=3)
+    assert info["iterations"] == 3 and not info["success"]
+    xg, info = q.newton_step(H, 1.0, x, 2, eps=1e-10, max_it=0)
+    assert info["iterations"] == 0 and not info["success"]
+
+
+def test_singular_jacobian_is_reported():
+    # t = 0: h = gamma (x^d - 1); at x = 0 the Jacobian gamma d x^(d-1) vanishes
+    import paper_1109_0545_amd as q
+
+    s = config_system(CONFIGS["n8_dd"])
+    S = q.System.from_synth(s)
+    H = q.Homotopy(S, s.gamma)
+    x = np.zeros((s.n, 2, 2))
+    say("newton singular")
+    xg, info = q.newton_step(H, 0.0, x, 2, eps=1e-10, max_it=4)
+    assert info["singular"] == 1 and not info["success"] and info["iterations"] == 1
+    assert np.array_equal(xg, x)
+
+
+def test_quadratic_convergence_residuals():
+    import paper_1109_0545_amd as q
+
+    s = config_system(CONFIGS["n32_dd"])
+    S = q.System.from_synth(s)
+    H = q.Homotopy(S, s.gamma)
+    x = np.zeros((s.n, 2, 2))
+    x[:, :, 0] = s.zstar[:, :, 0] + 1e-5
+    res = []
+    say("newton quadratic n32")
+    for _ in range(4):
+        x, info = q.newton_step(H, 1.0, x, 2, eps=0.0, max_it=1)
+        res.append(info["residual_first"])
+    assert res[0] > 1e-9
+    # quadratic: each residual at most a modest constant times the square of the previous
+    assert res[1] <= 100 * res[0] ** 2
+    assert res[2] <= max(100 * res[1] ** 2, 1e-28)
+    assert res[3] < 1e-28

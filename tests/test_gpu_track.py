@@ -1,0 +1,105 @@
+"""Path tracker (Algorithm 3.1) on the GPU: endpoints vs the oracle's exact
+root z**, closed-form paths, invariants, failure forcing."""
+
+import math
+from fractions import Fraction
+
+import mpmath
+import numpy as np
+import pytest
+
+from oracle.numbers import mpc_of
+from oracle.track import correct_digits
+from synth.systems import CONFIGS, config_system, start_root
+from tests.gpu_helpers import fixture, say, zss_mpc
+from tests.test_oracle_track import branch, decoupled_system
+
+pytestmark = pytest.mark.gpu
+
+
+def track_config(name, L=None, **kw):
+    import paper_1109_0545_amd as q
+
+    fix = fixture(name)
+    s = config_system(CONFIGS[name])
+    L = L or s.L
+    S = q.System.from_synth(s)
+    H = q.Homotopy(S, s.gamma)
+    x0 = start_root(np.array(fix["degrees"]), np.array(fix["start_k"]), L)
+    p = q.default_track_params(**kw)
+    say("track", name, "L", L, kw)
+    z, st, _ = q.track_path(H, x0, L, p)
+    return z, st, zss_mpc(fix)
+
+
+def test_track_n8_dd_endpoint_digits():
+    z, st, zss = track_config("n8_dd")
+    assert not st["fail"] and st["t_final"] == 1.0
+    assert st["corrections"] >= st["succ_corrections"] > 0
+    assert correct_digits(z, zss) >= 28
+
+
+def test_track_n32_dd_endpoint_digits():
+    z, st, zss = track_config("n32_dd")
+    assert not st["fail"]
+    assert correct_digits(z, zss) >= 28
+
+
+def test_track_decoupled_closed_form():
+    import paper_1109_0545_amd as q
+
+    d = [3, 4]
+    c_turns = [Fraction(1, 7), Fraction(2, 5)]
+    s = decoupled_system(d, c_turns, Fraction(3, 11))
+    k = [1, 2]
+    S = q.System.from_synth(s)
+    H = q.Homotopy(S, s.gamma)
+    say("track decoupled")
+    z, st, _ = q.track_path(H, start_root(np.array(d), np.array(k), 2), 2)
+    assert not st["fail"]
+    g = complex(mpc_of(s.gamma))
+    for i in range(2):
+        ref = branch(d[i], k[i], complex(mpc_of(-s.coefs[2 * i + 1])), g, 1.0)
+        with mpmath.workprec(300):
+            zi = mpc_of(z[i])
+            # the exact root of x^d = c_stored nearest the branch endpoint
+            c = -mpc_of(s.coefs[2 * i + 1])
+            roots = [mpmath.root(c, d[i], j) for j in range(d[i])]
+            best = min(roots, key=lambda q_: abs(complex(q_) - ref))
+            assert abs(zi - best) < 1e-29
+
+
+def test_track_stop_criterion_forces_failure():
+    import paper_1109_0545_amd as q
+
+    s = config_system(CONFIGS["n8_dd"])
+    S = q.System.from_synth(s)
+    H = q.Homotopy(S, s.gamma)
+    x0 = start_root(s.degrees, np.zeros(s.n, np.int64), 2)
+    p = q.default_track_params(eps_path=0.0, max_it_path=1, lambda_min=0.009)
+    say("track forced stop")
+    z, st, _ = q.track_path(H, x0, 2, p)
+    assert st["fail"] == 1 and st["t_final"] == 0.0 and st["corrections"] == 1 and st["succ_corrections"] == 0
+    p = q.default_track_params(max_steps=3)
+    z, st, _ = q.track_path(H, x0, 2, p)
+    assert st["corrections"] == 3 and st["fail"] == 1
+
+
+def test_track_step_log_and_invariants():
+    import paper_1109_0545_amd as q
+
+    fix = fixture("n8_dd")
+    s = config_system(CONFIGS["n8_dd"])
+    S = q.System.from_synth(s)
+    H = q.Homotopy(S, s.gamma)
+    x0 = start_root(np.array(fix["degrees"]), np.array(fix["start_k"]), 2)
+    say("track log n8")
+    z, st, log = q.track_path(H, x0, 2, log_cap=10000)
+    assert len(log) == st["corrections"]
+    acc = [r["lam"] for r in log if r["accepted"]]
+    assert len(acc) == st["succ_corrections"]
+    assert abs(math.fsum(acc) - 1.0) < 1e-12
+    for lam in acc[:-1]:
+        j = math.log2(lam / 0.01)
+        assert j == round(j)
+    assert st["min_step"] == min(acc)

@@ -59,3 +59,17 @@ def test_err_units():
     assert err_units([1.0, 0.0], exact, Fraction(1), L) == 0.0
     assert err_units([1.0, 2.0**-106], exact, Fraction(1), L) == pytest.approx(1.0)
     assert err_units([1.0, 2.0**-103], exact, Fraction(2), L) == pytest.approx(float(Fraction(1, 2**103) / (2 * u)))
+
+
+def test_rounding_keeps_precision_of_high_precision_inputs():
+    # a value computed at high precision must not be re-rounded to the
+    # caller's default mpmath precision when split into limbs
+    import mpmath
+
+    from oracle.numbers import to_limbs_complex
+
+    with mpmath.workprec(400):
+        v = mpmath.mpc(1, -2) / 3
+    limbs = to_limbs_complex(v, 4)
+    assert abs(frac(limbs[0]) - Fraction(1, 3)) < Fraction(1, 2**200)
+    assert abs(frac(limbs[1]) + Fraction(2, 3)) < Fraction(1, 2**200)
