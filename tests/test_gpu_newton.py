@@ -110,21 +110,23 @@ def test_singular_jacobian_is_reported():
     assert np.array_equal(xg, x)
 
 
-def test_quadratic_convergence_residuals():
+def test_residual_sequence_matches_oracle():
+    # four single iterations from a perturbed planted root at t = 1: every
+    # residual agrees with the oracle's Newton run (quadratic convergence in
+    # the oracle is pinned separately)
     import paper_1109_0545_amd as q
+    from oracle.newton import newton
 
     s = config_system(CONFIGS["n32_dd"])
     S = q.System.from_synth(s)
     H = q.Homotopy(S, s.gamma)
     x = np.zeros((s.n, 2, 2))
     x[:, :, 0] = s.zstar[:, :, 0] + 1e-5
+    ref = newton(s.exps, s.coefs, s.poly_offsets, s.gamma, 1.0, x, eps=0.0, max_it=4, form="quotient").residuals
     res = []
-    say("newton quadratic n32")
+    say("newton residual sequence n32")
     for _ in range(4):
         x, info = q.newton_step(H, 1.0, x, 2, eps=0.0, max_it=1)
         res.append(info["residual_first"])
-    assert res[0] > 1e-9
-    # quadratic: each residual at most a modest constant times the square of the previous
-    assert res[1] <= 100 * res[0] ** 2
-    assert res[2] <= max(100 * res[1] ** 2, 1e-28)
-    assert res[3] < 1e-28
+    for a, b in zip(res, ref):
+        assert abs(a - b) <= 1e-6 * b + 1e-29, (res, ref)
