@@ -59,6 +59,14 @@ def solve(J: list, rhs: list, prec: int) -> list:
         return [s[k] for k in range(len(rhs))]
 
 
+def inv_norm_inf(J: list, prec: int) -> float:
+    """||J^{-1}||_inf (row sums of complex moduli of the inverse)."""
+    with mpmath.workprec(prec):
+        Ai = mpmath.inverse(mpmath.matrix(J))
+        n = Ai.rows
+        return float(max(sum(abs(Ai[i, j]) for j in range(n)) for i in range(n)))
+
+
 def cond_inf(J: list, prec: int) -> float:
     """kappa_inf(J) = ||J||_inf ||J^{-1}||_inf (row sums of complex moduli)."""
     with mpmath.workprec(prec):
@@ -102,7 +110,16 @@ def newton(exps, coefs, offsets, gamma, t, x, eps, max_it, prec=None, form="prod
     return NewtonRun(z, i, rho < eps, res)
 
 
-def newton_tolerance(n: int, kappa: float, L: int, dz_inf: float, z_inf: float) -> float:
-    """Bound on ||z_kernel - z_oracle||_inf after one step: 8 n kappa u ||dz|| + 2 u ||z||."""
+def newton_tolerance(n: int, kappa: float, L: int, dz_inf: float, z_inf: float, jinv_inf: float = 0.0,
+                     h_scale: float = 0.0) -> float:
+    """Bound on ||z_kernel - z_oracle||_inf after one step from the same input bits.
+
+    Three sources, added:
+      * the elimination, backward stable: 8 n kappa u ||dz||;
+      * the rounding of h in L-limb arithmetic, at most 64 u times its
+        componentwise scale S (the bound the evaluation parity tests hold),
+        carried into dz by J^{-1}: 64 u ||J^{-1}|| max_i S_i;
+      * the final update z + dz: 2 u ||z||.
+    """
     u = 2.0 ** (-53 * L)
-    return 8 * n * kappa * u * dz_inf + 2 * u * z_inf
+    return 8 * n * kappa * u * dz_inf + 64 * u * jinv_inf * h_scale + 2 * u * z_inf

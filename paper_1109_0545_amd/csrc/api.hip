@@ -130,7 +130,11 @@ static void free_ws(Workspace &w) {
   w = Workspace();
 }
 
-static size_t table_bytes(int n, int emax, int L) { return 2 * (size_t)n * (emax + 1) * 16 * L; }
+// LDS bytes of the evaluation kernel's two power tables (2L limb planes of
+// [emax+1][n rounded up to 32] doubles each)
+static size_t table_bytes(int n, int emax, int L) {
+  return 2 * 2 * (size_t)L * (emax + 1) * (((size_t)n + 31) & ~(size_t)31) * sizeof(double);
+}
 
 extern "C" qdp_status qdp_system_create(int32_t n, const int32_t *off, const uint8_t *exps, const double *coefs,
                                         qdp_prec prec, qdp_system **out) {
@@ -251,7 +255,9 @@ static qdp_status eval_common(const qdp_system *f, const qdp_homotopy *h, double
   if (!f) return fail(QDP_EINVAL, "NULL system");
   if (!valid_prec(L) || L > f->L) return fail(QDP_EINVAL, "prec must be 1, 2 or 4 and not above the system's");
   if (!x_dev || !y_dev || !jac_dev) return fail(QDP_EINVAL, "NULL buffer");
-  qdp::EvalOut o{jac_dev, f->n, 1, y_dev, 1, 1.0, scale_dev};
+  // row-major [i][v][2][L] and [i][2][L]: limb c at offset c
+  const long e = 2 * L;
+  qdp::EvalOut o{jac_dev, 1, (long)f->n * e, e, y_dev, 1, e, 1.0, scale_dev};
   HIPCHK(qdp::launch_eval(L, f->dev(), x_dev, hom_args(h, L, t, h != nullptr), o, nullptr, st));
   return QDP_OK;
 }
@@ -327,8 +333,9 @@ static qdp_status enqueue_newton(qdp_homotopy *h, Workspace *w, int L, double t,
   const qdp_system *f = h->f;
   const int n = f->n;
   HIPCHK(qdp::launch_init_state(w->st, eps, max_it, st));
-  const size_t e = 2 * (size_t)L;
-  qdp::EvalOut o{w->ab, 1, n, w->ab + (size_t)n * n * e, 1, -1.0, w->scale};
+  // [A | -h] column-major in limb planes: limb c of (r,k) at c*n(n+1) + k*n + r
+  const long ps = (long)n * (n + 1);
+  qdp::EvalOut o{w->ab, ps, 1, n, w->ab + (size_t)n * n, ps, 1, -1.0, w->scale};
   const qdp::HomArgs ha = hom_args(h, L, t, 1);
   const bool timing = g_timing != 0;
   if (timing) {

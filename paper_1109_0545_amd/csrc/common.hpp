@@ -24,14 +24,15 @@ struct DevSystem {
   const int32_t *deg;      // [n] total degree d_i of f_i
 };
 
-// Where evaluation results go.  Complex multiword elements of 2L doubles;
-// strides count elements.  J(i,v) -> J + (i*rsJ + v*csJ)*2L,
-// value_i -> y + i*sy*2L (times ysign), scale_i -> scale[i] (nullable).
+// Where evaluation results go.  All strides count doubles.  Limb c of the
+// complex element J(i,v) (c < L real limbs, then L imaginary limbs) sits at
+// J[c*psJ + i*rsJ + v*csJ]; limb c of value i at y[c*psy + i*sy] (times
+// ysign); scale_i -> scale[i] (nullable).
 struct EvalOut {
   double *J;
-  long rsJ, csJ;
+  long psJ, rsJ, csJ;
   double *y;
-  long sy;
+  long psy, sy;
   double ysign;
   double *scale;
 };

@@ -10,11 +10,14 @@ hipError_t launch_eval_dd(const DevSystem &, const double *, const HomArgs &, co
 hipError_t launch_eval_qd(const DevSystem &, const double *, const HomArgs &, const EvalOut &, const NewtonState *,
                           hipStream_t);
 
+// LDS of the evaluation kernel (512 threads = 8 wavefronts): two power
+// tables of 2L limb planes [emax+1][n rounded up to 32], or the cross-wave
+// reduction buffer of 2L planes [8][n+1] plus 8 scale sums, whichever is larger
 size_t eval_lds_bytes(int L, const DevSystem &s) {
-  const size_t el = 16 * (size_t)L;
-  size_t tables = 2 * (size_t)s.n * (s.emax + 1) * el;
-  size_t red = 16 * (size_t)(s.n + 1) * el + 16 * sizeof(double);
-  return tables > red ? tables : red;
+  const size_t nv = ((size_t)s.n + 31) & ~(size_t)31;
+  const size_t tables = 2 * 2 * (size_t)L * (s.emax + 1) * nv;
+  const size_t red = 2 * (size_t)L * 8 * (s.n + 1) + 8;
+  return (tables > red ? tables : red) * sizeof(double);
 }
 
 hipError_t launch_eval(int L, const DevSystem &s, const double *x, const HomArgs &h, const EvalOut &o,

@@ -5,24 +5,25 @@
 // every partial derivative); how each monomial is differentiated follows the
 // reverse-mode (Speelpenning) products of Section 6: with g_v = x_v^(a_v) the
 // factor of variable v, the partial of c * prod_v g_v with respect to x_v is
-//     c * (prod_{w<v} g_w) * (prod_{w>v} g_w) * a_v x_v^(a_v - 1),
-// i.e. a prefix product times a suffix product times a derivative factor.
-// Powers x_v^e and e x_v^(e-1) come from a table built once per evaluation in
-// LDS (the common factor x^(a-1) of Section 6 folded into the table), so each
-// variable of a monomial costs four complex products, as the paper's scheme.
+//     c * (product of the factors before v) * (product of the factors after v)
+//       * a_v x_v^(a_v - 1),
+// for any fixed order of the variables.  Powers x_v^e and e x_v^(e-1) come
+// from a table built once per evaluation in LDS (the common factor x^(a-1) of
+// Section 6 folded into the table), so each variable of a monomial costs four
+// complex products, as the paper's scheme.
 //
 // Mapping on CDNA4: one workgroup per polynomial; a monomial is spread over
-// LM lanes of a wavefront, each lane owning C consecutive variables (dense
-// exponent rows, coalesced byte loads).  Within a lane the suffix products of
-// its chunk are formed sequentially; across the LM lanes the chunk products
-// are combined by a Hillis-Steele scan in both directions (wavefront
-// shuffles); each lane then walks its chunk forward once.  A lane keeps the
-// running sums of its C Jacobian entries in registers over all monomials it
-// visits; the per-polynomial reduction is a fixed-order shuffle butterfly then
-// a fixed-order LDS sum across wavefronts (no atomics: results are
-// bit-reproducible).  The homotopy blend and the b = -h column are written
-// directly in the layout the eliminator reads.
-
+// LM lanes of a wavefront and lane g owns the CH variables g, g+LM, g+2LM, ...
+// (interleaved, so that neighbouring lanes read neighbouring table entries).
+// The order used for the prefix/suffix products is lane-major: a lane first
+// forms the suffix products of its own variables, the LM lanes then combine
+// their chunk products with Hillis-Steele scans in both directions (wavefront
+// shuffles), and each lane walks its variables forward once.  A lane keeps
+// the running sums of its CH Jacobian entries in registers over all the
+// monomials it visits; the per-polynomial reduction is a fixed-order shuffle
+// butterfly then a fixed-order LDS sum across wavefronts (no atomics: results
+// are bit-reproducible).  Tables and the reduction buffer are stored as limb
+// planes so that a wavefront's LDS accesses hit consecutive banks.
 #pragma once
 #include "common.hpp"
 
@@ -37,30 +38,36 @@ template <int L> struct EvalArgs {
   const NewtonState *gate;
 };
 
+// row stride (doubles) of a table plane: a multiple of 32 so that lanes with
+// consecutive variables read consecutive banks whatever their exponents
+__host__ __device__ inline int table_stride(int n) { return (n + 31) & ~31; }
+
 template <int L, int CH, int LM, int NT>
 __global__ __launch_bounds__(NT) void k_eval(EvalArgs<L> a) {
-  constexpr int G = 64 / LM;   // monomials per wavefront at a time
-  constexpr int W = NT / 64;   // wavefronts
+  constexpr int G = 64 / LM;  // monomials per wavefront at a time
+  constexpr int W = NT / 64;  // wavefronts
   constexpr int SLOTS = W * G;
   if (a.gate && !a.gate->active) return;
 
   extern __shared__ double smem[];
   const int n = a.s.n;
   const int E1 = a.s.emax + 1;
-  C<L> *Gt = reinterpret_cast<C<L> *>(smem);  // [n][E1] x^e
-  C<L> *Qt = Gt + n * E1;                     // [n][E1] e x^(e-1)
+  const int nv = table_stride(n);
+  const size_t tps = (size_t)E1 * nv;  // plane size of one table
+  double *Gt = smem;                   // x_v^e          plane c at Gt + c*tps + e*nv + v
+  double *Qt = smem + 2 * L * tps;     // e x_v^(e-1)
   const int tid = threadIdx.x;
 
   // ---- power tables
   for (int v = tid; v < n; v += NT) {
-    C<L> xv = cload<L>(a.x + (size_t)v * 2 * L);
+    const C<L> xv = cload<L>(a.x + (size_t)v * 2 * L);
     C<L> p = cone<L>();
-    Gt[v * E1] = p;
-    Qt[v * E1] = czero<L>();
+    pstore<L>(Gt + v, tps, p);
+    pstore<L>(Qt + v, tps, czero<L>());
     for (int e = 1; e < E1; ++e) {
-      Qt[v * E1 + e] = cmul_d<L>(p, (double)e);
+      pstore<L>(Qt + (size_t)e * nv + v, tps, cmul_d<L>(p, (double)e));
       p = cmul<L>(p, xv);
-      Gt[v * E1 + e] = p;
+      pstore<L>(Gt + (size_t)e * nv + v, tps, p);
     }
   }
   __syncthreads();
@@ -70,7 +77,6 @@ __global__ __launch_bounds__(NT) void k_eval(EvalArgs<L> a) {
   const int lane = tid & 63, wave = tid >> 6;
   const int grp = lane / LM, gl = lane % LM;
   const int slot = wave * G + grp;
-  const int v0 = gl * CH;
   const int LS = a.s.LS;
 
   C<L> acc[CH];
@@ -79,25 +85,25 @@ __global__ __launch_bounds__(NT) void k_eval(EvalArgs<L> a) {
   C<L> accv = czero<L>();
   double accS = 0.0;
 
-  auto gval = [&](int v, int e) -> C<L> { return v < n ? Gt[v * E1 + e] : cone<L>(); };
-  auto qval = [&](int v, int e) -> C<L> { return v < n ? Qt[v * E1 + e] : czero<L>(); };
+  auto gval = [&](int v, int e) -> C<L> { return v < n ? pload<L>(Gt + (size_t)e * nv + v, tps) : cone<L>(); };
+  auto qval = [&](int v, int e) -> C<L> { return v < n ? pload<L>(Qt + (size_t)e * nv + v, tps) : czero<L>(); };
 
   for (int base = t0; base < t1; base += SLOTS) {
     const int j = base + slot;
     const bool valid = j < t1;
     const int jj = valid ? j : t0;
-    const uint8_t *er = a.s.exps + (size_t)jj * a.s.npad + v0;
+    const uint8_t *er = a.s.exps + (size_t)jj * a.s.npad + gl;
     int ex[CH];
 #pragma unroll
-    for (int k = 0; k < CH; ++k) ex[k] = er[k];
+    for (int k = 0; k < CH; ++k) ex[k] = er[k * LM];
     const C<L> coef = cload_trunc<L>(a.s.coefs + (size_t)jj * 2 * LS, LS);
 
-    // suffix products inside the chunk (exclusive), and the chunk product
+    // suffix products of this lane's variables (exclusive), and their product
     C<L> sfx[CH];
     sfx[CH - 1] = cone<L>();
 #pragma unroll
-    for (int k = CH - 2; k >= 0; --k) sfx[k] = cmul<L>(sfx[k + 1], gval(v0 + k + 1, ex[k + 1]));
-    const C<L> chunk = cmul<L>(sfx[0], gval(v0, ex[0]));
+    for (int k = CH - 2; k >= 0; --k) sfx[k] = cmul<L>(sfx[k + 1], gval(gl + (k + 1) * LM, ex[k + 1]));
+    const C<L> chunk = cmul<L>(sfx[0], gval(gl, ex[0]));
 
     // inclusive scans of chunk products over the LM lanes of this monomial
     C<L> fw = chunk, bw = chunk;
@@ -113,13 +119,15 @@ __global__ __launch_bounds__(NT) void k_eval(EvalArgs<L> a) {
     if (LM == 1 || gl == 0) pre = cone<L>();
     if (LM == 1 || gl == LM - 1) suf = cone<L>();
 
-    // walk the chunk: running = c * prefix(all before v) * suffix(all after chunk)
+    // walk this lane's variables: run = c * (all factors before v)
+    //                                   * (all factors of later lanes)
     C<L> run = cmul<L>(cmul<L>(coef, pre), suf);
 #pragma unroll
     for (int k = 0; k < CH; ++k) {
-      C<L> d = cmul<L>(cmul<L>(run, sfx[k]), qval(v0 + k, ex[k]));
+      const int v = gl + k * LM;
+      C<L> d = cmul<L>(cmul<L>(run, sfx[k]), qval(v, ex[k]));
       if (valid) acc[k] = cadd<L>(acc[k], d);
-      run = cmul<L>(run, gval(v0 + k, ex[k]));
+      run = cmul<L>(run, gval(v, ex[k]));
     }
     // lane 0 of the group now holds c * x^a (the monomial value)
     if (valid && gl == 0) {
@@ -137,14 +145,18 @@ __global__ __launch_bounds__(NT) void k_eval(EvalArgs<L> a) {
     accS += __shfl_xor(accS, off, 64);
   }
   __syncthreads();  // tables no longer needed: reuse LDS for the cross-wave sum
-  C<L> *red = reinterpret_cast<C<L> *>(smem);  // [W][n+1]
-  double *redS = reinterpret_cast<double *>(red + W * (n + 1));
+  const int rn = n + 1;
+  const size_t rps = (size_t)W * rn;  // plane size of the reduction buffer [W][n+1]
+  double *red = smem;
+  double *redS = smem + 2 * L * rps;
   if (lane < LM) {
 #pragma unroll
-    for (int k = 0; k < CH; ++k)
-      if (v0 + k < n) red[wave * (n + 1) + v0 + k] = acc[k];
+    for (int k = 0; k < CH; ++k) {
+      const int v = gl + k * LM;
+      if (v < n) pstore<L>(red + (size_t)wave * rn + v, rps, acc[k]);
+    }
     if (lane == 0) {
-      red[wave * (n + 1) + n] = accv;
+      pstore<L>(red + (size_t)wave * rn + n, rps, accv);
       redS[wave] = accS;
     }
   }
@@ -152,8 +164,8 @@ __global__ __launch_bounds__(NT) void k_eval(EvalArgs<L> a) {
 
   // ---- fixed-order sum over wavefronts, homotopy blend, store
   for (int col = tid; col <= n; col += NT) {
-    C<L> s = red[col];
-    for (int w = 1; w < W; ++w) s = cadd<L>(s, red[w * (n + 1) + col]);
+    C<L> s = pload<L>(red + col, rps);
+    for (int w = 1; w < W; ++w) s = cadd<L>(s, pload<L>(red + (size_t)w * rn + col, rps));
     if (col < n) {
       C<L> Jv = s;
       if (a.h.homotopy) {
@@ -173,7 +185,7 @@ __global__ __launch_bounds__(NT) void k_eval(EvalArgs<L> a) {
           }
         }
       }
-      cstore<L>(a.o.J + ((size_t)i * a.o.rsJ + (size_t)col * a.o.csJ) * 2 * L, Jv);
+      pstore<L>(a.o.J + (size_t)i * a.o.rsJ + (size_t)col * a.o.csJ, a.o.psJ, Jv);
     } else {
       C<L> hv = s;
       double S = 0.0;
@@ -194,7 +206,7 @@ __global__ __launch_bounds__(NT) void k_eval(EvalArgs<L> a) {
         S = fabs(a.h.t) * S + cabs_hi<L>(w) * (cabs_hi<L>(pd) + 1.0);
       }
       if (a.o.ysign < 0) hv = cneg<L>(hv);
-      cstore<L>(a.o.y + (size_t)i * a.o.sy * 2 * L, hv);
+      pstore<L>(a.o.y + (size_t)i * a.o.sy, a.o.psy, hv);
       if (a.o.scale) a.o.scale[i] = S;
     }
   }

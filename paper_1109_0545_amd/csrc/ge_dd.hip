@@ -9,7 +9,7 @@ template <int L>
 static hipError_t launch_ge_L(int n, double *ab, double *scale, double *x, double *dz, NewtonState *st,
                               hipStream_t s) {
   GeArgs<L> a{n, ab, scale, x, dz, st};
-  constexpr int NT = 512;
+  constexpr int NT = (L == 4) ? 512 : 1024;
   const bool fit = ge_lds_bytes(L, n, true) <= 160 * 1024;
   if (fit) {
     const size_t lds = ge_lds_bytes(L, n, true);

@@ -2,21 +2,26 @@
 // substitution and the update z := z + dz of one Newton iteration
 // (Algorithm 4.1 and the description of GE / Back_Subs in Section 4).
 //
-// Section 4 selects as pivot the largest number in the current column, then
-// lets every thread update its own rows, then solves the triangular system.
-// Here one workgroup owns the whole system: the augmented matrix sits in LDS
-// when it fits (n <= 64 in double-double), otherwise in global memory (L2).
-// The matrix is column-major (column k holds a_{rk} for all rows r, the
-// right-hand side b = -h is column n), so a wavefront reading one column
-// reads consecutive addresses.  Rows are never swapped: the not-yet-pivoted
-// rows form a list that is compacted each step (double-buffered), and each
-// elimination step spreads the remaining rows times remaining columns over
-// all threads with one barrier per step.  The pivot key is |Re| + |Im| of the
-// leading limb (FP64), ties to the lowest row index; every wavefront finds the
-// pivot on its own, so no extra barrier is needed.  The inverse of each pivot
-// is kept for the back substitution, which one wavefront runs column by
-// column with register shuffles.
-
+// Section 4 lets one thread pick the pivot (the largest number in the
+// current column) while the others wait, then every thread updates its own
+// rows, with a barrier per column.  On one CDNA4 workgroup the pivot search
+// and the pivot's inverse would then sit on the critical path of every
+// column, so this kernel looks one column ahead:
+//   * during step j, wavefront 0 updates column j+1 of every remaining row
+//     first, finds the pivot of column j+1 in registers (largest |Re|+|Im| of
+//     the leading limb, ties to the lowest row), forms its inverse and
+//     publishes both in LDS;
+//   * meanwhile the other wavefronts update columns j+2..n (the right-hand
+//     side b = -h is column n);
+//   * one barrier per column.
+// The augmented matrix is column-major and split into limb planes (a
+// wavefront reading one column reads consecutive doubles of each plane, so
+// LDS accesses hit consecutive banks); it sits in LDS when it fits, else in
+// global memory.
+// Rows are never swapped: the not-yet-pivoted rows form an ordered list,
+// compacted each step without reordering (double-buffered).  The pivot
+// inverses are kept for the back substitution, which one wavefront runs
+// column by column with register shuffles.
 #pragma once
 #include "common.hpp"
 
@@ -25,9 +30,9 @@ using namespace mw;
 
 template <int L> struct GeArgs {
   int n;
-  double *ab;     // column-major (n+1) x n complex, element (r,k) at (k*n + r)*2L
+  double *ab;     // column-major (n+1) x n complex in 2L limb planes: limb c of (r,k) at c*n(n+1) + k*n + r
   double *scale;  // [n] FP64 componentwise scale of h (nullable -> 1)
-  double *x;      // [n][2][L] current point, updated in place
+  double *x;      // [n][2][L] current point, updated in place (nullable)
   double *dz;     // [n][2][L] correction out (nullable)
   NewtonState *st;
 };
@@ -44,136 +49,249 @@ template <int NT> __device__ double block_max(double v, double *buf) {
   return r;
 }
 
+// Pack a nonnegative FP64 pivot key and a row index into one 64-bit word
+// whose unsigned order is (key descending, then row ascending), so that the
+// argmax over a wavefront is a max over one word.  The key contributes the
+// high word of its FP64 bit pattern (sign, exponent, 20 mantissa bits), which
+// is monotone for nonnegative doubles; keys within a relative 1e-6 of each
+// other tie and go to the lowest row, which partial pivoting tolerates.
+// 0 = no candidate (NaN or no row); a high word of zero marks a zero column.
+__device__ inline unsigned long long pack_key(double key, int row) {
+  const bool ok = key == key && key >= 0.0;
+  const unsigned int kb = ok ? (unsigned int)(__double_as_longlong(key) >> 32) + 1u : 0u;
+  return ((unsigned long long)kb << 32) | (unsigned int)(0x7fffffff - row);
+}
+__device__ inline int unpack_row(unsigned long long w) { return 0x7fffffff - (int)(w & 0xffffffffu); }
+__device__ inline bool packed_nonzero(unsigned long long w) { return (w >> 32) > 1u; }
+
+__device__ inline unsigned long long wave_max_u64(unsigned long long w) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long ow = __shfl_xor(w, o, 64);
+    w = ow > w ? ow : w;
+  }
+  return w;
+}
+
+// broadcast lane `src` (wave-uniform) of a complex multiword value
+template <int L> __device__ inline C<L> cbcast(const C<L> &a, int src) {
+  C<L> r;
+#pragma unroll
+  for (int k = 0; k < L; ++k) {
+    r.re.v[k] = __shfl(a.re.v[k], src, 64);
+    r.im.v[k] = __shfl(a.im.v[k], src, 64);
+  }
+  return r;
+}
+
 template <int L, int NT, bool IN_LDS>
 __global__ __launch_bounds__(NT) void k_ge(GeArgs<L> a) {
   if (a.st && !a.st->active) return;
   extern __shared__ double smem[];
   const int n = a.n;
-  const int tid = threadIdx.x, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr int E2 = 2 * L;
 
-  // LDS carve-up
+  // ---- LDS carve-up
   size_t off = 0;
   double *Mlds = smem;
   if (IN_LDS) off += (size_t)n * (n + 1) * E2;
-  C<L> *invp = reinterpret_cast<C<L> *>(smem + off);
+  C<L> *invp = reinterpret_cast<C<L> *>(smem + off);  // [n] pivot inverses
   off += (size_t)n * E2;
-  C<L> *bb = reinterpret_cast<C<L> *>(smem + off);
+  double *bb = smem + off;  // [n] back-substitution rhs, limb planes of n
   off += (size_t)n * E2;
-  double *redbuf = smem + off;
+  double *redbuf = smem + off;  // [16]
   off += 16;
-  int *act0 = reinterpret_cast<int *>(smem + off);
-  int *act1 = act0 + n;
-  int *perm = act1 + n;
-  int *flags = perm + n;  // [0] singular
+  int *list0 = reinterpret_cast<int *>(smem + off);
+  int *list1 = list0 + n;
+  int *perm = list1 + n;  // [n] pivot row of each column
+  // parity-indexed control words written one step ahead by wavefront 0:
+  // ctl[j & 1] = slot of the pivot of column j in the list of step j,
+  // ctl[2 + (j & 1)] = column j has no nonzero pivot
+  int *ctl = perm + n;
 
   double *M = IN_LDS ? Mlds : a.ab;
-  auto at = [&](int r, int k) -> double * { return M + ((size_t)k * n + r) * E2; };
+  const size_t PS = (size_t)n * (n + 1);  // plane size
+  auto at = [&](int r, int k) -> double * { return M + (size_t)k * n + r; };
 
   if (IN_LDS) {
-    const size_t tot = (size_t)n * (n + 1) * E2;
+    const size_t tot = PS * E2;
     for (size_t q = tid; q < tot; q += NT) Mlds[q] = a.ab[q];
   }
-  for (int r = tid; r < n; r += NT) act0[r] = r;
-  if (tid == 0) flags[0] = 0;
+  for (int r = tid; r < n; r += NT) list0[r] = r;
   __syncthreads();
 
   // ---- residual rho = max_i |h_i|_1 / max_i S_i (leading limbs, FP64)
   double hb = 0.0, sb = 0.0;
   for (int r = tid; r < n; r += NT) {
-    const C<L> b = cload<L>(at(r, n));
+    const C<L> b = pload<L>(at(r, n), PS);
     hb = fmax(hb, cabs1_hi<L>(b));
-    if (!cfinite<L>(b)) hb = __builtin_nan("");
+    if (!cfinite<L>(b)) hb = __builtin_inf();
     sb = fmax(sb, a.scale ? a.scale[r] : 1.0);
   }
-  // NaN must survive the max: encode it as +inf for the reduction
-  const double hb_r = block_max<NT>(__builtin_isnan(hb) ? __builtin_inf() : hb, redbuf);
+  const double hb_r = block_max<NT>(hb, redbuf);
   const double sb_r = block_max<NT>(sb, redbuf);
-  const double rho = (hb_r == __builtin_inf()) ? __builtin_nan("") : (sb_r > 0.0 ? hb_r / sb_r : hb_r);
+  const bool bad = !(hb_r < __builtin_inf());
+  const double rho = bad ? __builtin_nan("") : (sb_r > 0.0 ? hb_r / sb_r : hb_r);
+
+  // Wavefront 0: given the current values v of column c in the rows of the
+  // list `lst` (slot s -> row lst_row(s), R rows, at most 64*RPL per lane),
+  // choose the pivot, form its inverse, store the multipliers v * inv of the
+  // other rows into column c, publish pivot row / slot / inverse / singular.
+  double pmax = 0.0, pmin = __builtin_inf();
+
+  // ---- column 0: pivot and multipliers (wavefront 0)
+  if (wave == 0) {
+    unsigned long long best = 0;
+    for (int s = lane; s < n; s += 64) {
+      const unsigned long long w = pack_key(cabs1_hi<L>(pload<L>(at(s, 0), PS)), s);
+      best = w > best ? w : best;
+    }
+    best = wave_max_u64(best);
+    const bool sing = !packed_nonzero(best) || bad;
+    const int p0 = unpack_row(best);
+    if (!sing) {
+      const C<L> pv = pload<L>(at(p0, 0), PS);
+      const C<L> inv = cinv<L>(pv);
+      for (int s = lane; s < n; s += 64)
+        if (s != p0) pstore<L>(at(s, 0), PS, cmul<L>(pload<L>(at(s, 0), PS), inv));
+      if (lane == 0) {
+        invp[0] = inv;
+        const double k = cabs1_hi<L>(pv);
+        pmax = k;
+        pmin = k;
+      }
+    }
+    if (lane == 0) {
+      ctl[2] = sing ? 1 : 0;
+      ctl[0] = p0;  // the initial list is the identity: slot = row
+      perm[0] = p0;
+    }
+  }
+  __syncthreads();
 
   // ---- elimination
-  double pmax = 0.0, pmin = __builtin_inf();
-  int *cur = act0, *nxt = act1;
-  bool singular = !(rho == rho);  // NaN residual: skip the solve
+  int *cur = list0, *nxt = list1;
+  bool singular = ctl[2] != 0;
+  int steps_done = 0;
   for (int j = 0; j < n && !singular; ++j) {
-    const int K = n - j;
-    // pivot search (every wavefront, identical result)
-    double best = -1.0;
-    int bestr = 0x7fffffff, bests = 0;
-    for (int s = lane; s < K; s += 64) {
-      const int r = cur[s];
-      const double key = cabs1_hi<L>(cload<L>(at(r, j)));
-      const double kk = (key == key) ? key : -1.0;
-      if (kk > best || (kk == best && r < bestr)) {
-        best = kk;
-        bestr = r;
-        bests = s;
-      }
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ob = __shfl_xor(best, o, 64);
-      const int orr = __shfl_xor(bestr, o, 64);
-      const int os = __shfl_xor(bests, o, 64);
-      if (ob > best || (ob == best && orr < bestr)) {
-        best = ob;
-        bestr = orr;
-        bests = os;
-      }
-    }
-    if (!(best > 0.0)) {  // zero (or NaN) column: singular
-      singular = true;
-      break;
-    }
-    const int p = bestr;
-    const C<L> inv = cinv<L>(cload<L>(at(p, j)));
-    pmax = fmax(pmax, best);
-    pmin = fmin(pmin, best);
-    if (tid == 0) {
-      invp[j] = inv;
-      perm[j] = p;
-    }
-    const int R = K - 1;
+    const int K = n - j;  // rows in the list (the pivot row included)
+    const int R = K - 1;  // rows to update
+    const int p = perm[j];
+    const int pos = ctl[j & 1];
+    // slot s of the rows to update -> row (the list without the pivot, order kept)
+    auto row_of = [&](int s) { return cur[s + (s >= pos ? 1 : 0)]; };
     if (R > 0) {
-      // compacted list without p: slot s -> row (cur[s] == p ? cur[K-1] : cur[s])
-      for (int s = tid; s < R; s += NT) {
-        const int r = cur[s];
-        nxt[s] = (r == p) ? cur[K - 1] : r;
-      }
-      const int P = NT / R > 0 ? NT / R : 1;
-      for (int q = tid; q < R * P; q += NT) {
-        const int s = q % R, ph = q / R;
-        int r = cur[s];
-        if (r == p) r = cur[K - 1];
-        const C<L> l = cmul<L>(cload<L>(at(r, j)), inv);
-        for (int k = j + 1 + ph; k <= n; k += P) {
-          double *e = at(r, k);
-          cstore<L>(e, cfms<L>(cload<L>(e), l, cload<L>(at(p, k))));
+      if (wave == 0) {
+        // look-ahead: update column j+1, choose its pivot, store its multipliers
+        const C<L> up = pload<L>(at(p, j + 1), PS);
+        unsigned long long best = 0;
+        constexpr int RPL = 4;  // rows per lane kept in registers (n <= 256)
+        C<L> vals[RPL];
+        int rows[RPL];
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) {
+          const int s = lane + 64 * u;
+          rows[u] = -1;
+          vals[u] = czero<L>();
+          if (s < R) {
+            const int r = row_of(s);
+            const C<L> v = cfms<L>(pload<L>(at(r, j + 1), PS), pload<L>(at(r, j), PS), up);
+            vals[u] = v;
+            rows[u] = r;
+            nxt[s] = r;
+            const unsigned long long w = pack_key(cabs1_hi<L>(v), r);
+            best = w > best ? w : best;
+          }
+        }
+        best = wave_max_u64(best);
+        const bool sing = !packed_nonzero(best);
+        const int p1 = unpack_row(best);
+        // the lane holding the pivot value broadcasts it
+        int owner = 0, ou = 0;
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) {
+          const unsigned long long m = __ballot(rows[u] == p1);
+          if (m) {
+            owner = __builtin_ffsll(m) - 1;
+            ou = u;
+          }
+        }
+        C<L> pv = vals[0];
+#pragma unroll
+        for (int u = 1; u < RPL; ++u)
+          if (ou == u) pv = vals[u];
+        pv = cbcast<L>(pv, owner);
+        if (!sing) {
+          const C<L> inv = cinv<L>(pv);
+#pragma unroll
+          for (int u = 0; u < RPL; ++u)
+            if (rows[u] >= 0) pstore<L>(at(rows[u], j + 1), PS, rows[u] == p1 ? vals[u] : cmul<L>(vals[u], inv));
+          if (lane == 0) {
+            invp[j + 1] = inv;
+            const double k = cabs1_hi<L>(pv);
+            pmax = fmax(pmax, k);
+            pmin = fmin(pmin, k);
+          }
+        }
+        if (lane == 0) {
+          ctl[2 + ((j + 1) & 1)] = sing ? 1 : 0;
+          ctl[(j + 1) & 1] = ou * 64 + owner;
+          perm[j + 1] = p1;
+        }
+      } else {
+        // trailing update of columns j+2..n: items (column, row slot) in
+        // column-major order spread evenly over wavefronts 1..
+        const int ncol = n - j - 1;
+        if (ncol > 0) {
+          constexpr int T = NT - 64;
+          const int items = R * ncol;
+          const int t = tid - 64;
+          if (t < items) {
+            const int dk = T / R, ds = T - dk * R;
+            int s = t % R, k = j + 2 + t / R;
+            for (int q = t; q < items; q += T) {
+              const int r = row_of(s);
+              double *e = at(r, k);
+              pstore<L>(e, PS, cfms<L>(pload<L>(e, PS), pload<L>(at(r, j), PS), pload<L>(at(p, k), PS)));
+              s += ds;
+              k += dk;
+              if (s >= R) {
+                s -= R;
+                k += 1;
+              }
+            }
+          }
         }
       }
     }
     __syncthreads();
+    singular = (R > 0) && ctl[2 + ((j + 1) & 1)] != 0;
+    steps_done = j + 1;
     int *tmp = cur;
     cur = nxt;
     nxt = tmp;
   }
+  if (steps_done < n) singular = true;
 
   // ---- back substitution (one wavefront) and update
-  if (!singular && tid < 64) {
-    for (int i = lane; i < n; i += 64) bb[i] = cload<L>(at(perm[i], n));
+  if (!singular && wave == 0) {
+    for (int i = lane; i < n; i += 64) pstore<L>(bb + i, n, pload<L>(at(perm[i], n), PS));
     for (int j = n - 1; j >= 0; --j) {
+      const int owner = j & 63;
       C<L> dj = czero<L>();
-      if (lane == (j & 63)) dj = cmul<L>(bb[j], invp[j]);
-      dj = cshfl<L>(dj, j & 63, 64);
-      for (int i = lane; i < j; i += 64) bb[i] = cfms<L>(bb[i], cload<L>(at(perm[i], j)), dj);
-      if (lane == (j & 63)) bb[j] = dj;
+      if (lane == owner) dj = cmul<L>(pload<L>(bb + j, n), invp[j]);
+      dj = cbcast<L>(dj, owner);
+      for (int i = lane; i < j; i += 64)
+        pstore<L>(bb + i, n, cfms<L>(pload<L>(bb + i, n), pload<L>(at(perm[i], j), PS), dj));
+      if (lane == owner) pstore<L>(bb + j, n, dj);
     }
   }
   __syncthreads();
   double dmax = 0.0;
   if (!singular) {
     for (int v = tid; v < n; v += NT) {
-      const C<L> d = bb[v];
+      const C<L> d = pload<L>(bb + v, n);
       if (a.dz) cstore<L>(a.dz + (size_t)v * E2, d);
       if (a.x) {
         double *xp = a.x + (size_t)v * E2;
@@ -190,8 +308,8 @@ __global__ __launch_bounds__(NT) void k_ge(GeArgs<L> a) {
     s->rho = rho;
     s->dz_norm = dmax;
     s->cond_est = (pmin > 0.0 && pmin < __builtin_inf()) ? pmax / pmin : __builtin_inf();
-    if (singular && rho == rho) s->singular = 1;
-    if (!(rho == rho)) s->nonfinite = 1;
+    if (singular && !bad) s->singular = 1;
+    if (bad) s->nonfinite = 1;
     s->success = (rho < s->eps) ? 1 : 0;
     s->active = (!singular && rho > s->eps && s->iterations < s->max_it) ? 1 : 0;
   }

@@ -320,24 +320,90 @@ template <int L> MW_DEV C<L> cmul(const C<L> &a, const C<L> &b) {
   }
 }
 
-// a - l*u
-template <int L> MW_DEV C<L> cfms(const C<L> &a, const C<L> &l, const C<L> &u) {
-  return csub<L>(a, cmul<L>(l, u));
+// double-double a + x1*y1 + x2*y2: both leading products exact, both sums
+// exact (TwoSum), every error and cross term folded into the tail, one
+// normalisation
+MW_DEV R<2> dd_fms3(const R<2> &a, const R<2> &x1, const R<2> &y1, const R<2> &x2, const R<2> &y2) {
+  double e1, e2, t1, t2;
+  double p1 = two_prod(x1.v[0], y1.v[0], e1);
+  double p2 = two_prod(x2.v[0], y2.v[0], e2);
+  double s = two_sum(a.v[0], p1, t1);
+  s = two_sum(s, p2, t2);
+  double t = a.v[1] + ((t1 + t2) + (e1 + e2));
+  t = __builtin_fma(x1.v[0], y1.v[1], t);
+  t = __builtin_fma(x1.v[1], y1.v[0], t);
+  t = __builtin_fma(x2.v[0], y2.v[1], t);
+  t = __builtin_fma(x2.v[1], y2.v[0], t);
+  R<2> r;
+  r.v[0] = fast_two_sum(s, t, r.v[1]);
+  return r;
 }
 
-// 1/a = conj(a)/|a|^2, with a power-of-two prescale against overflow
+// a - l*u
+template <int L> MW_DEV C<L> cfms(const C<L> &a, const C<L> &l, const C<L> &u) {
+  if constexpr (L == 2) {
+    // re: a.re - l.re u.re + l.im u.im ; im: a.im - l.re u.im - l.im u.re
+    return C<2>{dd_fms3(a.re, rneg<2>(l.re), u.re, l.im, u.im), dd_fms3(a.im, rneg<2>(l.re), u.im, rneg<2>(l.im), u.re)};
+  } else if constexpr (L == 1) {
+    C<1> r;
+    r.re.v[0] = __builtin_fma(l.im.v[0], u.im.v[0], __builtin_fma(-l.re.v[0], u.re.v[0], a.re.v[0]));
+    r.im.v[0] = __builtin_fma(-l.im.v[0], u.re.v[0], __builtin_fma(-l.re.v[0], u.im.v[0], a.im.v[0]));
+    return r;
+  } else {
+    return csub<L>(a, cmul<L>(l, u));
+  }
+}
+
+// 1/p: an FP64 seed conj(p)/|p|^2 (with a power-of-two prescale against
+// overflow), then Newton's iteration inv <- inv + inv (1 - p inv), which
+// doubles the number of correct bits per step (one step for double double,
+// two for quad double).
 template <int L> MW_DEV C<L> cinv(const C<L> &a) {
   double m = fmax(__builtin_fabs(a.re.v[0]), __builtin_fabs(a.im.v[0]));
   int ex = 0;
   if (m > 0.0 && m < __builtin_inf()) (void)frexp(m, &ex);
-  C<L> s{rldexp<L>(a.re, -ex), rldexp<L>(a.im, -ex)};
-  R<L> d = radd<L>(rmul<L>(s.re, s.re), rmul<L>(s.im, s.im));
-  R<L> one = rfrom<L>(1.0);
-  R<L> inv = rdiv<L>(one, d);
-  C<L> r{rmul<L>(s.re, inv), rneg<L>(rmul<L>(s.im, inv))};
-  r.re = rldexp<L>(r.re, -ex);
-  r.im = rldexp<L>(r.im, -ex);
-  return r;
+  const C<L> p{rldexp<L>(a.re, -ex), rldexp<L>(a.im, -ex)};
+  const double pr = p.re.v[0], pi = p.im.v[0];
+  const double r0 = 1.0 / __builtin_fma(pr, pr, pi * pi);
+  const double i0r = pr * r0, i0i = -pi * r0;
+  C<L> inv;
+  if constexpr (L == 1) {
+    inv.re.v[0] = i0r;
+    inv.im.v[0] = i0i;
+  } else {
+    // q = p * inv0 with inv0 an FP64 complex, to double-double accuracy
+    double e1, e2, t, u;
+    double qr = two_sum(two_prod(pr, i0r, e1), two_prod(-pi, i0i, e2), t);
+    t = t + (e1 + e2);
+    t = __builtin_fma(p.re.v[1], i0r, t);
+    t = __builtin_fma(-p.im.v[1], i0i, t);
+    double qi = two_sum(two_prod(pr, i0i, e1), two_prod(pi, i0r, e2), u);
+    u = u + (e1 + e2);
+    u = __builtin_fma(p.re.v[1], i0i, u);
+    u = __builtin_fma(p.im.v[1], i0r, u);
+    // e = 1 - q (1 - qr is exact: qr is within a few ulps of 1)
+    const double er = (1.0 - qr) - t;
+    const double ei = -(qi + u);
+    const double dr = __builtin_fma(i0r, er, -(i0i * ei));
+    const double di = __builtin_fma(i0r, ei, i0i * er);
+    C<2> d2;
+    d2.re.v[0] = two_sum(i0r, dr, d2.re.v[1]);
+    d2.im.v[0] = two_sum(i0i, di, d2.im.v[1]);
+    if constexpr (L == 2) {
+      inv = d2;
+    } else {
+      inv = czero<L>();
+      inv.re.v[0] = d2.re.v[0];
+      inv.re.v[1] = d2.re.v[1];
+      inv.im.v[0] = d2.im.v[0];
+      inv.im.v[1] = d2.im.v[1];
+      const C<L> e = csub<L>(cone<L>(), cmul<L>(p, inv));
+      inv = cadd<L>(inv, cmul<L>(inv, e));
+    }
+  }
+  inv.re = rldexp<L>(inv.re, -ex);
+  inv.im = rldexp<L>(inv.im, -ex);
+  return inv;
 }
 
 template <int L> MW_DEV C<L> cdiv(const C<L> &a, const C<L> &b) { return cmul<L>(a, cinv<L>(b)); }
@@ -383,6 +449,27 @@ template <int L> MW_DEV void cstore(double *p, const C<L> &a) {
   for (int k = 0; k < L; ++k) {
     p[k] = a.re.v[k];
     p[L + k] = a.im.v[k];
+  }
+}
+
+// A complex multiword number split into limb planes: limb k of the real part
+// at p[k*ps], limb k of the imaginary part at p[(L+k)*ps].  Consecutive
+// elements of a plane are consecutive doubles, so a wavefront reading
+// consecutive elements touches consecutive LDS banks.
+template <int L> MW_DEV C<L> pload(const double *p, size_t ps) {
+  C<L> r;
+#pragma unroll
+  for (int k = 0; k < L; ++k) {
+    r.re.v[k] = p[k * ps];
+    r.im.v[k] = p[(L + k) * ps];
+  }
+  return r;
+}
+template <int L> MW_DEV void pstore(double *p, size_t ps, const C<L> &a) {
+#pragma unroll
+  for (int k = 0; k < L; ++k) {
+    p[k * ps] = a.re.v[k];
+    p[(L + k) * ps] = a.im.v[k];
   }
 }
 

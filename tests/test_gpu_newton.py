@@ -4,7 +4,8 @@ import mpmath
 import numpy as np
 import pytest
 
-from oracle.newton import cond_inf, newton_step as o_newton_step, newton_tolerance
+from oracle.evaluate import eval_homotopy as o_eval_homotopy
+from oracle.newton import cond_inf, inv_norm_inf, newton_step as o_newton_step, newton_tolerance
 from oracle.numbers import mpc_of, to_limbs_complex
 from synth.systems import CONFIGS, config_system, start_root
 from tests.gpu_helpers import fixture, say, zss_mpc
@@ -29,11 +30,13 @@ def one_step_parity(name, L, t=0.5, form="product"):
     xg, info = q.newton_step(H, t, x, L, eps=0.0, max_it=1)
     assert info["iterations"] == 1 and not info["success"] and not info["singular"]
     ref = o_newton_step(s.exps, s.coefs, s.poly_offsets, s.gamma, t, x, form=form)
+    hs = o_eval_homotopy(s.exps, s.coefs, s.poly_offsets, s.gamma, t, x, form=form)
     with mpmath.workprec(600):
         kappa = cond_inf(ref.J, 300)
+        jinv = inv_norm_inf(ref.J, 300)
         dzn = max(float(abs(d)) for d in ref.dz)
         zn = max(float(abs(z)) for z in ref.z)
-        tol = newton_tolerance(s.n, kappa, L, dzn, zn)
+        tol = newton_tolerance(s.n, kappa, L, dzn, zn, jinv, float(max(hs.S)))
         err = max(float(abs(mpc_of(xg[v]) - ref.z[v])) for v in range(s.n))
     assert err <= tol, (err, tol, kappa)
     # the residual agrees to FP64 unless it sits at the rounding floor of L limbs
