@@ -118,6 +118,36 @@ def track_case(q, name, L):
             "fail": st["fail"]}
 
 
+def newton_rate(q, name: str, L: int, mode: int, steps: int, warmup: int, t: float = 0.5):
+    """Newton steps/s of one workload at fixed t with the convergence exit off;
+    returns (steps/s, ms/step, eval us/launch, solve us/launch, system)."""
+    import torch
+
+    from synth.systems import CONFIGS, config_system
+
+    sysm = config_system(CONFIGS[name])
+    with open(os.path.join(ROOT, "tests", "golden", f"path_{name}.json")) as fh:
+        fix = json.load(fh)
+    S = q.System.from_synth(sysm)
+    H = q.Homotopy(S, sysm.gamma)
+    stream = torch.cuda.current_stream()
+    x = torch.from_numpy(path_point(fix, L)).cuda()
+    q.newton_step_dev(H, t, x, L, mode, eps=0.0, max_it=warmup, stream=stream)
+    torch.cuda.synchronize()
+    q.binding.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    q.newton_step_dev(H, t, x, L, mode, eps=0.0, max_it=steps, stream=stream)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    q.binding.set_timing(False)
+    info = q.last_info(H, L, stream=stream)
+    if info["iterations"] != steps:
+        raise RuntimeError(f"{name}: only {info['iterations']} of {steps} Newton iterations ran: {info}")
+    eval_ms, solve_ms, launches = q.binding.last_timing(H, L, stream=stream)
+    return steps / el, el / steps * 1e3, eval_ms / launches * 1e3, solve_ms / launches * 1e3, sysm, info
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +156,7 @@ def main():
     ap.add_argument("--mode", choices=["full", "mixed"], default="full")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-paths", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the mixed-precision / n=128 comparison lines")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 256 MiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -133,7 +164,6 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     if args.copy_calibration:
@@ -146,57 +176,31 @@ def main():
         return
 
     import paper_1109_0545_amd as q
-    from synth.systems import CONFIGS, config_system
+    from synth.systems import CONFIGS
 
-    cfg = CONFIGS["n64_dd"]
-    sysm = config_system(cfg)
-    with open(os.path.join(ROOT, "tests", "golden", "path_n64_dd.json")) as fh:
-        fix = json.load(fh)
     L = 2
     t = 0.5
-    x0 = path_point(fix, L)
-    S = q.System.from_synth(sysm)
-    H = q.Homotopy(S, sysm.gamma)
     mode = q.SOLVE_FULL if args.mode == "full" else q.SOLVE_MIXED_IR
-    stream = torch.cuda.current_stream()
-    x = torch.from_numpy(x0).cuda()
-
-    # warmup (also converges onto the path point at t = 1/2)
-    q.newton_step_dev(H, t, x, L, mode, eps=0.0, max_it=args.warmup, stream=stream)
-    info_w = q.last_info(H, L, stream=stream)
-    torch.cuda.synchronize()
-
-    q.binding.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    q.newton_step_dev(H, t, x, L, mode, eps=0.0, max_it=args.steps, stream=stream)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    q.binding.set_timing(False)
-    info = q.last_info(H, L, stream=stream)
-    if info["iterations"] != args.steps:
-        raise RuntimeError(f"only {info['iterations']} of {args.steps} Newton iterations ran: {info}")
-    eval_ms, solve_ms, launches = q.binding.last_timing(H, L, stream=stream)
+    rate, ms, ev_us, ge_us, sysm, info = newton_rate(q, "n64_dd", L, mode, args.steps, args.warmup, t)
 
     n = sysm.n
     cm, ca = eval_ops(sysm.exps, sysm.poly_offsets)
     ge_flops = (ge_cfma(n) + bs_cfma(n)) * CFMA
     ev_flops = cm * CMUL + ca * CADD
-    ge_us = solve_ms / launches * 1e3
-    ev_us = eval_ms / launches * 1e3
     if ge_us >= ev_us:
-        dom, dom_flops, dom_us = "elimination (k_ge)", ge_flops, ge_us
+        dom, dom_flops, dom_us = "elimination (k_ge)" if mode == 0 else "mixed solve (k_mixed)", ge_flops, ge_us
     else:
         dom, dom_flops, dom_us = "evaluation (k_eval)", ev_flops, ev_us
     achieved = dom_flops / (dom_us * 1e-6) / 1e12
+    cfg = CONFIGS["n64_dd"]
     out = {
         "metric": METRIC,
-        "value": args.steps / el,
+        "value": rate,
         "unit": "Newton steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": el / args.steps * 1e3,
+        "ms_per_step": ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -205,7 +209,7 @@ def main():
         "config": {
             "workload": "n=64 sparse system, 64 monomials per polynomial, exponents uniform in {0..4}, "
                         "unit-circle coefficients, seed 2, complex double double, total-degree homotopy at t=0.5, "
-                        f"one path, {'FULL double-double elimination' if mode == 0 else 'FP64 LU + DD refinement'}",
+                        f"one path, {'full double-double elimination' if mode == 0 else 'FP64 LU + DD refinement'}",
             "n": n, "monomials_per_polynomial": cfg.m, "max_exponent": cfg.E, "limbs": L, "solve": args.mode,
         },
         "roofline": {
@@ -219,17 +223,26 @@ def main():
             "algorithmic_flops_per_launch": dom_flops,
             "avg_launch_us": dom_us,
         },
-        "kernels": {"eval_us": ev_us, "solve_us": ge_us, "eval_flops": ev_flops, "solve_flops": ge_flops,
-                    "timed_launches": launches},
-        "warmup_info": {k: info_w[k] for k in ("iterations", "residual_last")},
+        "kernels": {"eval_us": ev_us, "solve_us": ge_us, "eval_flops": ev_flops, "solve_flops": ge_flops},
     }
+    if not args.no_extra:
+        extra = []
+        for name, md, k in (("n64_dd", 1 - mode, max(args.steps // 2, 10)), ("n128_dd", 0, 200), ("n128_dd", 1, 200)):
+            r, m_, e_, g_, _, inf = newton_rate(q, name, L, md, k, 10, t)
+            extra.append({"workload": name, "solve": "full" if md == 0 else "mixed", "steps_per_s": r,
+                          "ms_per_step": m_, "eval_us": e_, "solve_us": g_, "refine_steps": inf["refine_steps"]})
+        out["solve_modes"] = extra
     if not args.no_paths:
         try:
             out["paths"] = [track_case(q, "n8_dd", 2), track_case(q, "n32_dd", 2)]
         except Exception as e:  # report, never hide, a failing path
             out["paths"] = [{"error": str(e)}]
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sysm, x0, t)
+        from synth.systems import config_system
+
+        with open(os.path.join(ROOT, "tests", "golden", "path_n64_dd.json")) as fh:
+            fix = json.load(fh)
+        out["cpu_baseline"] = cpu_baseline(config_system(cfg), path_point(fix, L), t)
     print(json.dumps(out))
 
 

@@ -35,7 +35,7 @@ using qdp::NewtonState;
 // ------------------------------------------------------------------ errors
 
 static thread_local std::string g_err;
-static const bool kMixedBuilt = false;
+static const bool kMixedBuilt = true;
 static int g_timing = 0;
 
 static qdp_status fail(qdp_status s, const std::string &msg) {

@@ -84,61 +84,35 @@ template <int L> __device__ inline C<L> cbcast(const C<L> &a, int src) {
   return r;
 }
 
-template <int L, int NT, bool IN_LDS>
-__global__ __launch_bounds__(NT) void k_ge(GeArgs<L> a) {
-  if (a.st && !a.st->active) return;
-  extern __shared__ double smem[];
-  const int n = a.n;
+// Shared state of one elimination in LDS.
+template <int L> struct ElimLds {
+  C<L> *invp;  // [n] pivot inverses
+  int *list0, *list1;
+  int *perm;   // [n] pivot row of each column
+  int *ctl;    // [4] parity-indexed control words (see eliminate)
+};
+
+// Gaussian elimination with partial pivoting of the column-major matrix M
+// (n rows, n+1 columns, 2L limb planes PS apart), one workgroup of NT
+// threads; the last column is the right-hand side and is eliminated too.
+// Multipliers are stored in place of the eliminated entries; perm[j] is the
+// pivot row of column j and invp[j] the inverse of its pivot.  Returns false
+// when a column has no nonzero pivot.  Must be called by every thread.
+//
+// Wavefront 0 looks one column ahead: during step j it updates column j+1 of
+// every remaining row, finds that column's pivot (largest |Re|+|Im| of the
+// leading limb; see pack_key), forms its inverse and stores the multipliers
+// of column j+1, and publishes pivot row / list slot / inverse / singular
+// flag in parity-indexed LDS words (ctl[j & 1] = slot of the pivot of column
+// j in the list of step j, ctl[2 + (j & 1)] = column j has no nonzero pivot),
+// while the other wavefronts update columns j+2..n.  One barrier per column.
+template <int L, int NT>
+__device__ bool eliminate(double *M, size_t PS, int n, const ElimLds<L> &e, bool bad, double &pmax, double &pmin) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  constexpr int E2 = 2 * L;
-
-  // ---- LDS carve-up
-  size_t off = 0;
-  double *Mlds = smem;
-  if (IN_LDS) off += (size_t)n * (n + 1) * E2;
-  C<L> *invp = reinterpret_cast<C<L> *>(smem + off);  // [n] pivot inverses
-  off += (size_t)n * E2;
-  double *bb = smem + off;  // [n] back-substitution rhs, limb planes of n
-  off += (size_t)n * E2;
-  double *redbuf = smem + off;  // [16]
-  off += 16;
-  int *list0 = reinterpret_cast<int *>(smem + off);
-  int *list1 = list0 + n;
-  int *perm = list1 + n;  // [n] pivot row of each column
-  // parity-indexed control words written one step ahead by wavefront 0:
-  // ctl[j & 1] = slot of the pivot of column j in the list of step j,
-  // ctl[2 + (j & 1)] = column j has no nonzero pivot
-  int *ctl = perm + n;
-
-  double *M = IN_LDS ? Mlds : a.ab;
-  const size_t PS = (size_t)n * (n + 1);  // plane size
   auto at = [&](int r, int k) -> double * { return M + (size_t)k * n + r; };
-
-  if (IN_LDS) {
-    const size_t tot = PS * E2;
-    for (size_t q = tid; q < tot; q += NT) Mlds[q] = a.ab[q];
-  }
-  for (int r = tid; r < n; r += NT) list0[r] = r;
-  __syncthreads();
-
-  // ---- residual rho = max_i |h_i|_1 / max_i S_i (leading limbs, FP64)
-  double hb = 0.0, sb = 0.0;
-  for (int r = tid; r < n; r += NT) {
-    const C<L> b = pload<L>(at(r, n), PS);
-    hb = fmax(hb, cabs1_hi<L>(b));
-    if (!cfinite<L>(b)) hb = __builtin_inf();
-    sb = fmax(sb, a.scale ? a.scale[r] : 1.0);
-  }
-  const double hb_r = block_max<NT>(hb, redbuf);
-  const double sb_r = block_max<NT>(sb, redbuf);
-  const bool bad = !(hb_r < __builtin_inf());
-  const double rho = bad ? __builtin_nan("") : (sb_r > 0.0 ? hb_r / sb_r : hb_r);
-
-  // Wavefront 0: given the current values v of column c in the rows of the
-  // list `lst` (slot s -> row lst_row(s), R rows, at most 64*RPL per lane),
-  // choose the pivot, form its inverse, store the multipliers v * inv of the
-  // other rows into column c, publish pivot row / slot / inverse / singular.
-  double pmax = 0.0, pmin = __builtin_inf();
+  C<L> *invp = e.invp;
+  int *perm = e.perm, *ctl = e.ctl;
+  for (int r = tid; r < n; r += NT) e.list0[r] = r;
 
   // ---- column 0: pivot and multipliers (wavefront 0)
   if (wave == 0) {
@@ -170,8 +144,7 @@ __global__ __launch_bounds__(NT) void k_ge(GeArgs<L> a) {
   }
   __syncthreads();
 
-  // ---- elimination
-  int *cur = list0, *nxt = list1;
+  int *cur = e.list0, *nxt = e.list1;
   bool singular = ctl[2] != 0;
   int steps_done = 0;
   for (int j = 0; j < n && !singular; ++j) {
@@ -252,8 +225,8 @@ __global__ __launch_bounds__(NT) void k_ge(GeArgs<L> a) {
             int s = t % R, k = j + 2 + t / R;
             for (int q = t; q < items; q += T) {
               const int r = row_of(s);
-              double *e = at(r, k);
-              pstore<L>(e, PS, cfms<L>(pload<L>(e, PS), pload<L>(at(r, j), PS), pload<L>(at(p, k), PS)));
+              double *ep = at(r, k);
+              pstore<L>(ep, PS, cfms<L>(pload<L>(ep, PS), pload<L>(at(r, j), PS), pload<L>(at(p, k), PS)));
               s += ds;
               k += dk;
               if (s >= R) {
@@ -272,24 +245,101 @@ __global__ __launch_bounds__(NT) void k_ge(GeArgs<L> a) {
     cur = nxt;
     nxt = tmp;
   }
-  if (steps_done < n) singular = true;
+  return !singular && steps_done == n;
+}
 
-  // ---- back substitution (one wavefront) and update
-  if (!singular && wave == 0) {
-    for (int i = lane; i < n; i += 64) pstore<L>(bb + i, n, pload<L>(at(perm[i], n), PS));
-    for (int j = n - 1; j >= 0; --j) {
-      const int owner = j & 63;
-      C<L> dj = czero<L>();
-      if (lane == owner) dj = cmul<L>(pload<L>(bb + j, n), invp[j]);
-      dj = cbcast<L>(dj, owner);
-      for (int i = lane; i < j; i += 64)
-        pstore<L>(bb + i, n, cfms<L>(pload<L>(bb + i, n), pload<L>(at(perm[i], j), PS), dj));
-      if (lane == owner) pstore<L>(bb + j, n, dj);
-    }
+// Back substitution by wavefront 0 on the eliminated matrix: returns through
+// the limb planes of `out` (n elements, plane stride n) the solution of the
+// upper triangle (rows perm[0..n-1]) with right-hand side rhs_of(i) for the
+// pivot-ordered index i.
+template <int L, typename Rhs>
+__device__ void back_substitute(const double *M, size_t PS, int n, const int *perm, const C<L> *invp, double *out,
+                                Rhs rhs_of) {
+  const int lane = threadIdx.x & 63;
+  auto at = [&](int r, int k) -> const double * { return M + (size_t)k * n + r; };
+  for (int i = lane; i < n; i += 64) pstore<L>(out + i, n, rhs_of(i));
+  for (int j = n - 1; j >= 0; --j) {
+    const int owner = j & 63;
+    C<L> dj = czero<L>();
+    if (lane == owner) dj = cmul<L>(pload<L>(out + j, n), invp[j]);
+    dj = cbcast<L>(dj, owner);
+    for (int i = lane; i < j; i += 64)
+      pstore<L>(out + i, n, cfms<L>(pload<L>(out + i, n), pload<L>(at(perm[i], j), PS), dj));
+    if (lane == owner) pstore<L>(out + j, n, dj);
+  }
+}
+
+template <int L, int NT>
+__device__ double residual_of(const double *bcol, size_t PS, int n, const double *scale, double *redbuf, bool &bad) {
+  const int tid = threadIdx.x;
+  double hb = 0.0, sb = 0.0;
+  for (int r = tid; r < n; r += NT) {
+    const C<L> b = pload<L>(bcol + r, PS);
+    hb = fmax(hb, cabs1_hi<L>(b));
+    if (!cfinite<L>(b)) hb = __builtin_inf();
+    sb = fmax(sb, scale ? scale[r] : 1.0);
+  }
+  const double hb_r = block_max<NT>(hb, redbuf);
+  const double sb_r = block_max<NT>(sb, redbuf);
+  bad = !(hb_r < __builtin_inf());
+  return bad ? __builtin_nan("") : (sb_r > 0.0 ? hb_r / sb_r : hb_r);
+}
+
+__device__ inline void newton_bookkeeping(NewtonState *s, double rho, bool singular, bool bad, double dmax,
+                                          double pmax, double pmin) {
+  s->iterations += 1;
+  if (s->iterations == 1) s->rho_first = rho;
+  s->rho = rho;
+  s->dz_norm = dmax;
+  s->cond_est = (pmin > 0.0 && pmin < __builtin_inf()) ? pmax / pmin : __builtin_inf();
+  if (singular && !bad) s->singular = 1;
+  if (bad) s->nonfinite = 1;
+  s->success = (rho < s->eps) ? 1 : 0;
+  s->active = (!singular && rho > s->eps && s->iterations < s->max_it) ? 1 : 0;
+}
+
+template <int L, int NT, bool IN_LDS>
+__global__ __launch_bounds__(NT) void k_ge(GeArgs<L> a) {
+  if (a.st && !a.st->active) return;
+  extern __shared__ double smem[];
+  const int n = a.n;
+  const int tid = threadIdx.x, wave = tid >> 6;
+  constexpr int E2 = 2 * L;
+
+  // ---- LDS carve-up
+  size_t off = 0;
+  double *Mlds = smem;
+  if (IN_LDS) off += (size_t)n * (n + 1) * E2;
+  ElimLds<L> el;
+  el.invp = reinterpret_cast<C<L> *>(smem + off);
+  off += (size_t)n * E2;
+  double *bb = smem + off;  // [n] back-substitution vector, limb planes of n
+  off += (size_t)n * E2;
+  double *redbuf = smem + off;  // [16]
+  off += 16;
+  el.list0 = reinterpret_cast<int *>(smem + off);
+  el.list1 = el.list0 + n;
+  el.perm = el.list1 + n;
+  el.ctl = el.perm + n;
+
+  double *M = IN_LDS ? Mlds : a.ab;
+  const size_t PS = (size_t)n * (n + 1);  // plane size
+  if (IN_LDS) {
+    const size_t tot = PS * E2;
+    for (size_t q = tid; q < tot; q += NT) Mlds[q] = a.ab[q];
   }
   __syncthreads();
+
+  bool bad = false;
+  const double rho = residual_of<L, NT>(M + (size_t)n * n, PS, n, a.scale, redbuf, bad);
+  double pmax = 0.0, pmin = __builtin_inf();
+  const bool ok = eliminate<L, NT>(M, PS, n, el, bad, pmax, pmin);
+  if (ok && wave == 0)
+    back_substitute<L>(M, PS, n, el.perm, el.invp, bb,
+                       [&](int i) { return pload<L>(M + (size_t)n * n + el.perm[i], PS); });
+  __syncthreads();
   double dmax = 0.0;
-  if (!singular) {
+  if (ok) {
     for (int v = tid; v < n; v += NT) {
       const C<L> d = pload<L>(bb + v, n);
       if (a.dz) cstore<L>(a.dz + (size_t)v * E2, d);
@@ -301,18 +351,7 @@ __global__ __launch_bounds__(NT) void k_ge(GeArgs<L> a) {
     }
   }
   dmax = block_max<NT>(dmax, redbuf);
-  if (tid == 0 && a.st) {
-    NewtonState *s = a.st;
-    s->iterations += 1;
-    if (s->iterations == 1) s->rho_first = rho;
-    s->rho = rho;
-    s->dz_norm = dmax;
-    s->cond_est = (pmin > 0.0 && pmin < __builtin_inf()) ? pmax / pmin : __builtin_inf();
-    if (singular && !bad) s->singular = 1;
-    if (bad) s->nonfinite = 1;
-    s->success = (rho < s->eps) ? 1 : 0;
-    s->active = (!singular && rho > s->eps && s->iterations < s->max_it) ? 1 : 0;
-  }
+  if (tid == 0 && a.st) newton_bookkeeping(a.st, rho, !ok, bad, dmax, pmax, pmin);
 }
 
 }  // namespace qdp

@@ -121,10 +121,4 @@ hipError_t launch_arith(int op, int L, int64_t count, const double *a, const dou
   return hipGetLastError();
 }
 
-// Mixed-precision solve: not yet built
-hipError_t launch_mixed_solve(int, double *, double *, double *, NewtonState *, double *, double *, int,
-                              hipStream_t) {
-  return hipErrorNotSupported;
-}
-
 }  // namespace qdp

@@ -17,7 +17,7 @@ def limbs_point(vals, L):
     return np.stack([to_limbs_complex(mpmath.mpc(v), L) for v in vals])
 
 
-def one_step_parity(name, L, t=0.5, form="product"):
+def one_step_parity(name, L, t=0.5, form="product", mode=0):
     import paper_1109_0545_amd as q
 
     s = config_system(CONFIGS[name])
@@ -26,8 +26,8 @@ def one_step_parity(name, L, t=0.5, form="product"):
     x = limbs_point([complex(a, b) for a, b in fix["x_half_f64"]], L)
     S = q.System.from_synth(s)
     H = q.Homotopy(S, s.gamma)
-    say("newton one step", name, "L", L, "t", t)
-    xg, info = q.newton_step(H, t, x, L, eps=0.0, max_it=1)
+    say("newton one step", name, "L", L, "t", t, "mode", mode)
+    xg, info = q.newton_step(H, t, x, L, mode=mode, eps=0.0, max_it=1)
     assert info["iterations"] == 1 and not info["success"] and not info["singular"]
     ref = o_newton_step(s.exps, s.coefs, s.poly_offsets, s.gamma, t, x, form=form)
     hs = o_eval_homotopy(s.exps, s.coefs, s.poly_offsets, s.gamma, t, x, form=form)
@@ -58,6 +58,60 @@ def test_one_step_n32_dd():
 
 def test_one_step_n64_qd():
     one_step_parity("n64_qd", 4, form="quotient")
+
+
+@pytest.mark.parametrize("name", ["n8_dd", "n32_dd"])
+def test_one_step_mixed_precision(name):
+    # FP64 factorization + double-double refinement: same bound as the full
+    # double-double solve (the refinement reaches the double-double level)
+    one_step_parity(name, 2, form="quotient", mode=1)
+
+
+@pytest.mark.parametrize("name", ["n64_dd", "n128_dd"])
+def test_mixed_precision_converges_to_target_root(name):
+    import paper_1109_0545_amd as q
+
+    fix = fixture(name)
+    s = config_system(CONFIGS[name])
+    S = q.System.from_synth(s)
+    H = q.Homotopy(S, s.gamma)
+    x = np.zeros((s.n, 2, 2))
+    x[:, :, 0] = s.zstar[:, :, 0]
+    say("newton mixed converge", name)
+    xg, info = q.newton_step(H, 1.0, x, 2, mode=q.SOLVE_MIXED_IR, eps=64 * 2.0**-106, max_it=6)
+    zss = zss_mpc(fix)
+    with mpmath.workprec(600):
+        err = max(float(abs(mpc_of(xg[v]) - zss[v])) for v in range(s.n))
+    assert info["success"] and info["refine_steps"] >= 1
+    assert err <= 1e4 * 2.0**-106, err
+
+
+def test_mixed_precision_refinement_contracts():
+    # the textbook iterative-refinement property: from a point off the root the
+    # refinement of one Newton correction contracts and stops at the
+    # double-double level within its three steps
+    import paper_1109_0545_amd as q
+
+    s = config_system(CONFIGS["n32_dd"])
+    S = q.System.from_synth(s)
+    H = q.Homotopy(S, s.gamma)
+    x = np.zeros((s.n, 2, 2))
+    x[:, :, 0] = s.zstar[:, :, 0] + 1e-6
+    say("mixed refinement contraction")
+    _, info = q.newton_step(H, 1.0, x, 2, mode=q.SOLVE_MIXED_IR, eps=0.0, max_it=1)
+    assert 1 <= info["refine_steps"] <= 3
+    assert info["refine_err"] < 1e-28
+
+
+def test_mixed_precision_rejects_quad_double():
+    import paper_1109_0545_amd as q
+
+    s = config_system(CONFIGS["n8_dd"])
+    S = q.System.from_synth(s)
+    H = q.Homotopy(S, s.gamma)
+    with pytest.raises(q.QdpError) as e:
+        q.newton_step(H, 1.0, np.zeros((s.n, 2, 1)), 1, mode=q.SOLVE_MIXED_IR)
+    assert e.value.status == 5
 
 
 @pytest.mark.parametrize("name,L", [("n8_dd", 2), ("n32_dd", 2), ("n64_qd", 4), ("n64_dd", 2), ("n128_dd", 2)])
