@@ -118,6 +118,24 @@ def track_case(q, name, L):
             "fail": st["fail"]}
 
 
+def measured_traffic(kernel_file: str):
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary of
+    the dominant kernel, or None when the kernel's sources changed since the
+    counters were taken (the record stores a hash of those sources)."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", kernel_file)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as fh:
+            h.update(fh.read())
+    return rec["bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
+
+
 def newton_rate(q, name: str, L: int, mode: int, steps: int, warmup: int, t: float = 0.5):
     """Newton steps/s of one workload at fixed t with the convergence exit off;
     returns (steps/s, ms/step, eval us/launch, solve us/launch, system)."""
@@ -219,7 +237,7 @@ def main():
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic("traffic_k_ge_n64_dd.json") if dom.startswith("elimination") else None,
             "algorithmic_flops_per_launch": dom_flops,
             "avg_launch_us": dom_us,
         },
