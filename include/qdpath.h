@@ -129,7 +129,42 @@ qdp_status qdp_newton_step_dev(const qdp_homotopy *h, double t, double *x, qdp_p
 /* Synchronise hip_stream and return the info of the last Newton call on h at precision prec. */
 qdp_status qdp_homotopy_last_info(const qdp_homotopy *h, qdp_prec prec, qdp_newton_info *info, void *hip_stream);
 
+/* ---- learned step control (a growth direction of the tracker, not in the paper) ----
+ * A step-size network: widths w_0 (features) .. w_last (outputs), ReLU hidden
+ * layers; parameters are FP32, flat: for each layer its weights [out][in]
+ * (row-major) then its bias [out].  Outputs 0 .. w_last-2 are logits of
+ * "a step of lambda * 2^(k-1) would be accepted" (k = 0..w_last-2); the last
+ * output is the weight of the secant term in the predictor.  Training loss,
+ * over a batch of B rows with targets Y and a 0/1 mask M (both [B][w_last]):
+ *   (1/B) sum_b [ sum_{k<last} M_bk BCE(o_bk, Y_bk) + M_b,last (o_b,last - Y_b,last)^2 ]. */
 typedef struct qdp_policy qdp_policy;
+
+/* n_widths in [2, 9], widths in [1, 256], at least two outputs; params (host) FP32 in the flat
+ * layout; feat_mean / feat_std [w_0] (host) normalise raw features as (x - mean) / std (std > 0).
+ * Adam moments start at zero. */
+qdp_status qdp_policy_create(int32_t n_widths, const int32_t *widths, const float *params,
+                             const float *feat_mean, const float *feat_std, qdp_policy **out);
+void qdp_policy_destroy(qdp_policy *p);
+/* Synchronises the device and copies the FP32 parameters to host memory. */
+qdp_status qdp_policy_get_params(const qdp_policy *p, float *params);
+/* Loss and gradient of a batch (device pointers X [B][w_0] raw features, Y, M [B][w_last]).
+ * grad_out: device [n_params] or NULL (kept internally for qdp_policy_adam_step); loss_out: host
+ * or NULL (non-NULL synchronises the stream).  1 <= B <= 65536. */
+qdp_status qdp_policy_gradient(qdp_policy *p, const float *X, const float *Y, const float *M, int32_t B,
+                               float *grad_out, float *loss_out, void *hip_stream);
+/* One Adam step with bias correction: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr (m/(1-b1^t)) / (sqrt(v/(1-b2^t)) + eps); grad NULL uses the last internal gradient. */
+qdp_status qdp_policy_adam_step(qdp_policy *p, const float *grad, float lr, float b1, float b2, float eps,
+                                void *hip_stream);
+/* qdp_policy_gradient followed by qdp_policy_adam_step. */
+qdp_status qdp_policy_train_step(qdp_policy *p, const float *X, const float *Y, const float *M, int32_t B,
+                                 float lr, float b1, float b2, float eps, float *loss_out, void *hip_stream);
+/* Inference of B rows (device X raw features, Y outputs): use_bf16 != 0 uses the parameters
+ * rounded to BF16 (round to nearest even), else FP32; accumulation in FP32. */
+qdp_status qdp_policy_forward(const qdp_policy *p, const float *X, int32_t B, int32_t use_bf16, float *Y,
+                              void *hip_stream);
+/* One row from host features to host outputs with BF16 weights (synchronous). */
+qdp_status qdp_policy_infer_host(const qdp_policy *p, const float *x, float *y, void *hip_stream);
 
 typedef struct {
   double lambda0;       /* initial step size */
@@ -145,8 +180,16 @@ typedef struct {
   int32_t predictor;    /* qdp_pred */
   int64_t max_steps;    /* stop after this many corrections */
   int32_t mode;         /* qdp_solve */
-  int32_t pad;
+  int32_t probe;        /* data collection: at every accepted state, also try the step multipliers
+                           2^-1..2^3 and log a probe record (kind 1) per state; the path itself
+                           follows the plain rule */
   const qdp_policy *policy; /* learned step control (QDP_PRED_LEARNED), else NULL */
+  double lambda_max_learned; /* cap of the learned step size (0: 4 * lambda_max) */
+  double accept_threshold;   /* smallest acceptance probability a proposed multiplier may have (0: 0.3) */
+  int32_t policy_rule;       /* 0: the multiplier of largest expected progress p_k 2^(k-1) among those
+                                with p_k >= accept_threshold; 1: the largest multiplier with
+                                p_k >= accept_threshold */
+  int32_t pad2;
 } qdp_track_params;
 
 typedef struct {
@@ -162,27 +205,38 @@ typedef struct {
   double end_residual;       /* residual of the last end-refinement iteration */
   int64_t policy_used;       /* steps whose size came from the learned policy */
   int64_t policy_rejected;   /* learned proposals the Newton test rejected */
+  int64_t log_count;         /* records written to step_log */
+  int64_t probe_corrections; /* corrector stages spent on probes (probe mode) */
 } qdp_track_stats;
 
 /* Fill p with the default step-size control (lambda0 0.01, halving on failure,
  * doubling after 3 successes up to 0.08, lambda_min 0.01*2^-30, eps_path 1e-10,
  * 4 Newton iterations per correction, 10 at the end, secant predictor, full
- * working-precision solve). */
+ * working-precision solve, no probing; learned cap 0.32, expected-progress rule with
+ * probability floor 0.3). */
 qdp_status qdp_track_params_default(qdp_track_params *p);
 
-/* One step record written by qdp_track_path when step_log is not NULL. */
+/* Number of features of the learned step controller (the network's w_0). */
+#define QDP_POLICY_FEATURES 16
+/* Number of step multipliers it scores: 2^-1, 2^0, 2^1, 2^2, 2^3. */
+#define QDP_POLICY_MULTIPLIERS 5
+
+/* One record written by qdp_track_path when step_log is not NULL. */
 typedef struct {
   double t;          /* t before the step */
-  double lambda;     /* step size tried */
+  double lambda;     /* kind 0: step size tried; kind 1: the base step size of the multipliers */
   double rho_first;  /* Newton residual at the predicted point */
   double rho_last;   /* last Newton residual */
-  double dz_first;   /* not used (0) */
+  double dz_first;   /* ||dz||_inf of the first Newton iteration (the predictor's error) */
   double cond_est;
   double znorm;      /* ||z||_inf before the step */
   double pred_dist;  /* ||z_pred - z||_inf */
-  double corr_dist;  /* ||z_corrected - z_pred||_inf (accepted steps) */
+  double blend_label;/* kind 1: best secant weight for the 2^0 step (NaN when that step failed) */
+  float features[QDP_POLICY_FEATURES]; /* the learned controller's inputs in this state */
   int32_t iterations;
   int32_t accepted;
+  int32_t kind;      /* 0: a corrector stage of the path; 1: a probe record (no step taken) */
+  int32_t probe_ok;  /* kind 1: bit k set when the step lambda * 2^(k-1) converged, k = 0..4 */
 } qdp_step_record;
 
 /* Track one path from t = 0 to t = 1 (Algorithm 3.1): predict (secant
@@ -191,9 +245,16 @@ typedef struct {
  * the step size (step back and shrink on failure, expand after successes),
  * stop when the step is below lambda_min or after max_steps corrections; at
  * t = 1 refine the endpoint.  fail = (t < 1 at exit).
+ * With predictor = QDP_PRED_LEARNED and a policy, after every accepted step the
+ * network scores the multipliers 2^-1..2^3 of the last accepted step size (acceptance
+ * probabilities p_k); the multiplier chosen by policy_rule is tried (capped by
+ * lambda_max_learned and 1 - t; 2^-1 when no multiplier qualifies) with the predictor
+ * z + w r (z - z_prev), w the network's secant weight in [0, 1.5].  The Newton
+ * test judges: a failed correction steps back and falls back to the plain rule
+ * (shrink, secant) until the next success.
  *   x        : [n][2][prec] in: start solution at t = 0; out: end point
- *   step_log : NULL, or room for log_cap records; the number written is
- *              min(log_cap, corrections) */
+ *   step_log : NULL, or room for log_cap records; records are written in order
+ *              (corrector stages, plus probe records in probe mode) until full */
 qdp_status qdp_track_path(const qdp_homotopy *h, double *x, qdp_prec prec, const qdp_track_params *p,
                           qdp_track_stats *st, qdp_step_record *step_log, int64_t log_cap, void *hip_stream);
 

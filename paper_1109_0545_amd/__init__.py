@@ -16,6 +16,7 @@ from .binding import (  # noqa: F401
     SOLVE_FULL,
     SOLVE_MIXED_IR,
     Homotopy,
+    Policy,
     QdpError,
     System,
     arith_batch,

@@ -67,8 +67,12 @@ class TrackParams(ct.Structure):
         ("predictor", ct.c_int32),
         ("max_steps", ct.c_int64),
         ("mode", ct.c_int32),
-        ("pad", ct.c_int32),
+        ("probe", ct.c_int32),
         ("policy", ct.c_void_p),
+        ("lambda_max_learned", ct.c_double),
+        ("accept_threshold", ct.c_double),
+        ("policy_rule", ct.c_int32),
+        ("pad2", ct.c_int32),
     ]
 
 
@@ -86,10 +90,16 @@ class TrackStats(ct.Structure):
         ("end_residual", ct.c_double),
         ("policy_used", ct.c_int64),
         ("policy_rejected", ct.c_int64),
+        ("log_count", ct.c_int64),
+        ("probe_corrections", ct.c_int64),
     ]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+N_FEATURES = 16
+N_MULT = 5
 
 
 class StepRecord(ct.Structure):
@@ -102,9 +112,12 @@ class StepRecord(ct.Structure):
         ("cond_est", ct.c_double),
         ("znorm", ct.c_double),
         ("pred_dist", ct.c_double),
-        ("corr_dist", ct.c_double),
+        ("blend_label", ct.c_double),
+        ("features", ct.c_float * N_FEATURES),
         ("iterations", ct.c_int32),
         ("accepted", ct.c_int32),
+        ("kind", ct.c_int32),
+        ("probe_ok", ct.c_int32),
     ]
 
 
@@ -131,6 +144,15 @@ SIGNATURES = {
     "qdp_arith_batch": (ct.c_int, [ct.c_int32, ct.c_int, ct.c_int64, _P, _P, _P, _P, _P]),
     "qdp_set_timing": (ct.c_int, [ct.c_int32]),
     "qdp_homotopy_last_timing": (ct.c_int, [_P, ct.c_int, _D, _D, ct.POINTER(ct.c_int32), _P]),
+    "qdp_policy_create": (ct.c_int, [ct.c_int32, _P, _P, _P, _P, ct.POINTER(_P)]),
+    "qdp_policy_destroy": (None, [_P]),
+    "qdp_policy_get_params": (ct.c_int, [_P, _P]),
+    "qdp_policy_gradient": (ct.c_int, [_P, _P, _P, _P, ct.c_int32, _P, _P, _P]),
+    "qdp_policy_adam_step": (ct.c_int, [_P, _P, ct.c_float, ct.c_float, ct.c_float, ct.c_float, _P]),
+    "qdp_policy_train_step": (ct.c_int, [_P, _P, _P, _P, ct.c_int32, ct.c_float, ct.c_float, ct.c_float,
+                                         ct.c_float, _P, _P]),
+    "qdp_policy_forward": (ct.c_int, [_P, _P, ct.c_int32, ct.c_int32, _P, _P]),
+    "qdp_policy_infer_host": (ct.c_int, [_P, _P, _P, _P]),
     "qdp_last_error": (ct.c_char_p, []),
     "qdp_version": (ct.c_char_p, []),
 }
@@ -237,6 +259,62 @@ class Homotopy:
             pass
 
 
+class Policy:
+    """Step-size network (``qdp_policy``): FP32 master parameters on the device."""
+
+    def __init__(self, widths, params, feat_mean, feat_std):
+        self.widths = np.ascontiguousarray(widths, dtype=np.int32)
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        mu = np.ascontiguousarray(feat_mean, dtype=np.float32)
+        sd = np.ascontiguousarray(feat_std, dtype=np.float32)
+        h = _P()
+        _check(lib().qdp_policy_create(len(self.widths), _ptr(self.widths), _ptr(p), _ptr(mu), _ptr(sd),
+                                       ct.byref(h)))
+        self.handle = h
+        self.n_params = p.size
+        self.feat_mean, self.feat_std = mu, sd
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(self.n_params, dtype=np.float32)
+        _check(lib().qdp_policy_get_params(self.handle, _ptr(out)))
+        return out
+
+    def gradient(self, X, Y, M, grad_out=None, stream=None):
+        """Device tensors in; returns the loss (float); gradient into grad_out (device) if given."""
+        loss = ct.c_float()
+        _check(lib().qdp_policy_gradient(self.handle, _ptr(X), _ptr(Y), _ptr(M), X.shape[0], _ptr(grad_out),
+                                         ct.byref(loss), _stream(stream)))
+        return loss.value
+
+    def adam_step(self, grad=None, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+        _check(lib().qdp_policy_adam_step(self.handle, _ptr(grad), lr, b1, b2, eps, _stream(stream)))
+
+    def train_step(self, X, Y, M, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, want_loss=False, stream=None):
+        loss = ct.c_float()
+        _check(lib().qdp_policy_train_step(self.handle, _ptr(X), _ptr(Y), _ptr(M), X.shape[0], lr, b1, b2, eps,
+                                           ct.byref(loss) if want_loss else None, _stream(stream)))
+        return loss.value if want_loss else None
+
+    def forward(self, X, bf16=True, stream=None):
+        import torch
+
+        Y = torch.empty((X.shape[0], int(self.widths[-1])), dtype=torch.float32, device=X.device)
+        _check(lib().qdp_policy_forward(self.handle, _ptr(X), X.shape[0], 1 if bf16 else 0, _ptr(Y),
+                                        _stream(stream)))
+        return Y
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().qdp_policy_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 # ------------------------------------------------------------------ calls
 
 
@@ -297,6 +375,8 @@ def default_track_params(**overrides) -> TrackParams:
     p = TrackParams()
     _check(lib().qdp_track_params_default(ct.byref(p)))
     for k, v in overrides.items():
+        if k == "policy" and v is not None and not isinstance(v, int):
+            v = v.handle.value if hasattr(v.handle, "value") else v.handle
         setattr(p, k, v)
     return p
 
@@ -313,8 +393,12 @@ def track_path(h: Homotopy, x0: np.ndarray, prec: int, params: Optional[TrackPar
                                 _stream(stream)))
     recs = None
     if log is not None:
-        k = min(log_cap, st.corrections)
-        recs = [{f: getattr(log[i], f) for f, _ in StepRecord._fields_} for i in range(k)]
+        recs = []
+        for i in range(st.log_count):
+            r = log[i]
+            d = {f: getattr(r, f) for f, _ in StepRecord._fields_ if f != "features"}
+            d["features"] = np.ctypeslib.as_array(r.features).copy()
+            recs.append(d)
     return x, st.as_dict(), recs
 
 

@@ -23,7 +23,9 @@ hipError_t launch_arith(int op, int L, int64_t count, const double *a, const dou
                         double *out, hipStream_t s);
 hipError_t launch_init_state(NewtonState *st, double eps, int max_it, hipStream_t s);
 hipError_t launch_predict(int L, int n, const double *x, const double *xprev, double r, int have_prev,
-                          double *xpred, hipStream_t s);
+                          double *xpred, double *aux, hipStream_t s);
+hipError_t launch_blend_label(int L, int n, const double *x, const double *xprev, const double *xcorr, double *aux,
+                              hipStream_t s);
 hipError_t launch_copy(double *dst, const double *src, size_t count, hipStream_t s);
 hipError_t launch_mixed_solve(int n, double *ab, double *scale, double *x, NewtonState *st, double *lu,
                               double *work, int refinements, hipStream_t s);
@@ -50,6 +52,10 @@ static qdp_status fail(qdp_status s, const std::string &msg) {
   } while (0)
 
 extern "C" const char *qdp_last_error(void) { return g_err.c_str(); }
+
+namespace qdp {
+qdp_status set_error(qdp_status s, const std::string &msg) { return fail(s, msg); }
+}  // namespace qdp
 extern "C" const char *qdp_version(void) { return "qdpath 0.1 (gfx950)"; }
 
 static bool valid_prec(int p) { return p == 1 || p == 2 || p == 4; }
@@ -79,6 +85,7 @@ struct Workspace {
   double *lu = nullptr;     // mixed precision: FP64 factors
   double *work = nullptr;   // mixed precision scratch
   NewtonState *st = nullptr;
+  double *aux = nullptr;       // [4] predictor distance, blend-label sums
   std::vector<hipEvent_t> ev;  // timing: 3 events per iteration (before eval, between, after solve)
   int timed_its = 0;
 };
@@ -105,6 +112,7 @@ static qdp_status ensure_ws(qdp_homotopy *h, int L, Workspace **out) {
     HIPCHK(hipMalloc(&w.y, (size_t)n * e * sizeof(double)));
     HIPCHK(hipMalloc(&w.jac, (size_t)n * n * e * sizeof(double)));
     HIPCHK(hipMalloc(&w.st, sizeof(NewtonState)));
+    HIPCHK(hipMalloc(&w.aux, 4 * sizeof(double)));
     if (L == 2) {
       HIPCHK(hipMalloc(&w.lu, (size_t)n * (n + 1) * 2 * sizeof(double)));
       HIPCHK(hipMalloc(&w.work, (size_t)n * 8 * 2 * sizeof(double)));
@@ -126,6 +134,7 @@ static void free_ws(Workspace &w) {
   hipFree(w.lu);
   hipFree(w.work);
   hipFree(w.st);
+  hipFree(w.aux);
   for (auto &e : w.ev) hipEventDestroy(e);
   w = Workspace();
 }
@@ -483,15 +492,59 @@ extern "C" qdp_status qdp_track_params_default(qdp_track_params *p) {
   p->predictor = QDP_PRED_SECANT;
   p->max_steps = 2000000;
   p->mode = QDP_SOLVE_FULL;
+  p->probe = 0;
   p->policy = nullptr;
+  p->lambda_max_learned = 0.32;
+  p->accept_threshold = 0.3;
+  p->policy_rule = 0;
   return QDP_OK;
 }
 
-static double dev_norm_inf_host(const std::vector<double> &v, int n, int L) {
-  double m = 0;
-  for (int i = 0; i < n; ++i) m = std::max(m, std::fabs(v[(size_t)i * 2 * L]) + std::fabs(v[(size_t)i * 2 * L + L]));
-  return m;
+extern "C" qdp_status qdp_policy_infer_host(const qdp_policy *p, const float *x, float *y, void *hip_stream);
+
+namespace {
+
+// Host-side history the learned controller reads (all FP64, features are FP32).
+struct CtlHistory {
+  double lam_acc[3] = {0.01, 0.01, 0.01};  // last accepted step sizes, newest first
+  int run = 0;                              // consecutive successes
+  unsigned recent = 0;                      // accept bits of the last 8 attempts (bit 0 newest)
+  int attempts = 0;
+  int64_t accepted = 0;
+  // outcome of the last accepted correction
+  int iters = 0;
+  double rho_first = 1.0, rho_last = 1.0, cond = 1.0, dz_first = 0.0, znorm = 1.0, pred_dist = 0.0;
+};
+
+static double lg(double v, double lo) { return std::log10(std::max(v, lo)); }
+
+// The 16 inputs of the step-size network in the state after an accepted step.
+static void features(const CtlHistory &h, double t, float *f) {
+  const double zn = std::max(h.znorm, 1.0);
+  int rej = 0;
+  for (int k = 0; k < 8 && k < h.attempts; ++k) rej += ((h.recent >> k) & 1u) ? 0 : 1;
+  const double v[16] = {
+      std::log2(h.lam_acc[0] / 0.01),
+      std::log2(h.lam_acc[1] / 0.01),
+      std::log2(h.lam_acc[2] / 0.01),
+      (double)h.iters,
+      lg(h.rho_first, 1e-40) / 10.0,
+      lg(h.rho_last, 1e-40) / 10.0,
+      lg(h.cond, 1.0) / 5.0,
+      t,
+      lg(1.0 - t, 1e-16),
+      lg(h.znorm, 1e-300),
+      lg(h.pred_dist / zn, 1e-40) / 10.0,
+      lg(h.dz_first / zn, 1e-40) / 10.0,
+      std::min(h.run, 10) / 10.0,
+      rej / 8.0,
+      (lg(h.dz_first, 1e-300) - lg(h.pred_dist, 1e-300)) / 10.0,
+      std::min<double>((double)h.accepted, 1000.0) / 1000.0,
+  };
+  for (int k = 0; k < 16; ++k) f[k] = (float)v[k];
 }
+
+}  // namespace
 
 extern "C" qdp_status qdp_track_path(const qdp_homotopy *hc, double *x, qdp_prec prec, const qdp_track_params *pp,
                                      qdp_track_stats *stats, qdp_step_record *log, int64_t log_cap, void *stream) {
@@ -510,8 +563,13 @@ extern "C" qdp_status qdp_track_path(const qdp_homotopy *hc, double *x, qdp_prec
   if (p.mode == QDP_SOLVE_MIXED_IR && L != 2)
     return fail(QDP_EUNSUPPORTED, "mixed-precision refinement is implemented for double double");
   if (p.predictor == QDP_PRED_QUADRATIC) return fail(QDP_EUNSUPPORTED, "quadratic predictor not built");
-  if (p.predictor == QDP_PRED_LEARNED && !p.policy) return fail(QDP_EINVAL, "learned predictor needs a policy");
-  if (p.predictor == QDP_PRED_LEARNED) return fail(QDP_EUNSUPPORTED, "learned step control not built");
+  const bool learned = p.predictor == QDP_PRED_LEARNED;
+  if (learned && !p.policy) return fail(QDP_EINVAL, "learned predictor needs a policy");
+  if (p.predictor != QDP_PRED_SECANT && !learned) return fail(QDP_EINVAL, "unknown predictor");
+  const double lam_cap = learned ? (p.lambda_max_learned > 0 ? p.lambda_max_learned : 4 * p.lambda_max) : p.lambda_max;
+  const double thr = p.accept_threshold > 0 ? p.accept_threshold : 0.3;
+  if (thr >= 1.0) return fail(QDP_EINVAL, "accept_threshold must be below 1");
+  if (p.policy_rule != 0 && p.policy_rule != 1) return fail(QDP_EINVAL, "policy_rule must be 0 or 1");
   auto *h = const_cast<qdp_homotopy *>(hc);
   const int n = h->f->n;
   qdp_status s = check_point(n, L, x);
@@ -520,50 +578,119 @@ extern "C" qdp_status qdp_track_path(const qdp_homotopy *hc, double *x, qdp_prec
   Workspace *w = nullptr;
   if ((s = ensure_ws(h, L, &w)) != QDP_OK) return s;
   hipStream_t st = (hipStream_t)stream;
-  const size_t cnt = (size_t)n * 2 * L;
-  const size_t bytes = cnt * sizeof(double);
+  const size_t bytes = (size_t)n * 2 * L * sizeof(double);
   const auto t_start = std::chrono::steady_clock::now();
   HIPCHK(hipMemcpyAsync(w->x, x, bytes, hipMemcpyHostToDevice, st));
 
   std::memset(stats, 0, sizeof(*stats));
-  double t = 0.0, tprev = 0.0, lam = p.lambda0;
-  bool have_prev = false, stop = false;
+  double t = 0.0, tprev = 0.0, lam = p.lambda0, blend = 1.0;
+  bool have_prev = false, stop = false, from_policy = false;
   int run = 0;
-  int64_t succ = 0, corr = 0, nit = 0, nlog = 0;
+  int64_t succ = 0, corr = 0, nit = 0, nlog = 0, used = 0, rejected = 0, probes = 0;
   double sum_step = 0.0, min_step = INFINITY;
   NewtonState ns;
-  std::vector<double> hz(log ? cnt : 0), hp(log ? cnt : 0);
-  while (t < 1.0 && !stop) {
-    const double step = std::min(lam, 1.0 - t);
+  double aux[4] = {0, 0, 0, 0};
+  CtlHistory hist;
+  float feat[16];
+  auto push = [&](const qdp_step_record &r) {
+    if (log && nlog < log_cap) log[nlog++] = r;
+  };
+  // one corrector stage from the current accepted point with step `step` and secant weight `wgt`
+  auto correct = [&](double step, double wgt, double &tn_out) -> qdp_status {
     const double tn = (t + step >= 1.0) ? 1.0 : t + step;
-    const double r = have_prev ? (tn - t) / (t - tprev) : 0.0;
-    HIPCHK(qdp::launch_predict(L, n, w->x, w->xprev, r, have_prev ? 1 : 0, w->xw, st));
-    if (log) {
-      HIPCHK(hipMemcpyAsync(hz.data(), w->x, bytes, hipMemcpyDeviceToHost, st));
-      HIPCHK(hipMemcpyAsync(hp.data(), w->xw, bytes, hipMemcpyDeviceToHost, st));
-    }
-    if ((s = enqueue_newton(h, w, L, tn, w->xw, p.mode, p.eps_path, p.max_it_path, st)) != QDP_OK) return s;
+    tn_out = tn;
+    const double r = have_prev ? wgt * (tn - t) / (t - tprev) : 0.0;
+    HIPCHK(qdp::launch_predict(L, n, w->x, w->xprev, r, have_prev ? 1 : 0, w->xw, w->aux, st));
+    qdp_status e = enqueue_newton(h, w, L, tn, w->xw, p.mode, p.eps_path, p.max_it_path, st);
+    if (e != QDP_OK) return e;
     HIPCHK(hipMemcpyAsync(&ns, w->st, sizeof(ns), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(aux, w->aux, sizeof(aux), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    return QDP_OK;
+  };
+
+  while (t < 1.0 && !stop) {
+    // ---- probes (data collection): all multipliers from this accepted state
+    if (p.probe && have_prev) {
+      qdp_step_record rec;
+      std::memset(&rec, 0, sizeof(rec));
+      rec.kind = 1;
+      rec.t = t;
+      rec.lambda = hist.lam_acc[0];
+      rec.blend_label = NAN;
+      features(hist, t, rec.features);
+      for (int k = 0; k < 5; ++k) {
+        const double step = std::min(hist.lam_acc[0] * std::ldexp(1.0, k - 1), 1.0 - t);
+        double tn;
+        if ((s = correct(step, 1.0, tn)) != QDP_OK) return s;
+        ++probes;
+        if (ns.success) {
+          rec.probe_ok |= 1 << k;
+          if (k == 1) {
+            HIPCHK(qdp::launch_blend_label(L, n, w->x, w->xprev, w->xw, w->aux, st));
+            HIPCHK(hipMemcpyAsync(aux, w->aux, sizeof(aux), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            const double r = (tn - t) / (t - tprev);
+            if (aux[2] > 0) rec.blend_label = aux[1] / (r * aux[2]);
+          }
+        }
+      }
+      push(rec);
+    }
+    // ---- choose the step
+    double step = std::min(lam, 1.0 - t);
+    double wgt = 1.0;
+    from_policy = false;
+    if (learned && have_prev && run > 0) {
+      // after a success: the network proposes the multiplier and the secant weight
+      features(hist, t, feat);
+      float out[8];
+      if ((s = qdp_policy_infer_host(p.policy, feat, out, stream)) != QDP_OK) return s;
+      int best = -1;
+      double best_score = -1.0;
+      for (int k = 0; k < 5; ++k) {
+        const double pk = 1.0 / (1.0 + std::exp(-(double)out[k]));
+        if (pk < thr) continue;
+        const double score = p.policy_rule == 0 ? pk * std::ldexp(1.0, k - 1) : (double)k;
+        if (score > best_score) {
+          best_score = score;
+          best = k;
+        }
+      }
+      const double mult = best >= 0 ? std::ldexp(1.0, best - 1) : 0.5;
+      step = std::min(std::min(hist.lam_acc[0] * mult, lam_cap), 1.0 - t);
+      step = std::max(step, std::min(p.lambda_min, 1.0 - t));
+      wgt = std::min(std::max((double)out[5], 0.0), 1.5);
+      from_policy = true;
+    }
+    double tn;
+    if ((s = correct(step, wgt, tn)) != QDP_OK) return s;
     ++corr;
     nit += ns.iterations;
     const bool ok = ns.success != 0;
-    if (log && nlog < log_cap) {
-      qdp_step_record &rec = log[nlog++];
+    {
+      qdp_step_record rec;
       std::memset(&rec, 0, sizeof(rec));
+      rec.kind = 0;
       rec.t = t;
       rec.lambda = step;
       rec.rho_first = ns.rho_first;
       rec.rho_last = ns.rho;
+      rec.dz_first = ns.dz_first;
       rec.cond_est = ns.cond_est;
-      rec.znorm = dev_norm_inf_host(hz, n, L);
-      double pd = 0;
-      for (int i = 0; i < n; ++i)
-        pd = std::max(pd, std::fabs(hp[(size_t)i * 2 * L] - hz[(size_t)i * 2 * L]) +
-                              std::fabs(hp[(size_t)i * 2 * L + L] - hz[(size_t)i * 2 * L + L]));
-      rec.pred_dist = pd;
+      rec.znorm = hist.znorm;
+      rec.pred_dist = aux[0];
+      rec.blend_label = NAN;
+      features(hist, t, rec.features);
       rec.iterations = ns.iterations;
       rec.accepted = ok ? 1 : 0;
+      push(rec);
+    }
+    hist.recent = (hist.recent << 1) | (ok ? 1u : 0u);
+    hist.attempts += 1;
+    if (from_policy) {
+      ++used;
+      if (!ok) ++rejected;
     }
     if (ok) {
       // accept: (x_prev, t_prev) <- (x, t); (x, t) <- (corrected, tn)
@@ -575,15 +702,32 @@ extern "C" qdp_status qdp_track_path(const qdp_homotopy *hc, double *x, qdp_prec
       ++succ;
       sum_step += step;
       min_step = std::min(min_step, step);
-      if (++run >= p.expand_after) {
+      hist.lam_acc[2] = hist.lam_acc[1];
+      hist.lam_acc[1] = hist.lam_acc[0];
+      hist.lam_acc[0] = step;
+      hist.accepted = succ;
+      hist.iters = ns.iterations;
+      hist.rho_first = ns.rho_first;
+      hist.rho_last = ns.rho;
+      hist.cond = ns.cond_est;
+      hist.dz_first = ns.dz_first;
+      hist.znorm = ns.xnorm;
+      hist.pred_dist = aux[0];
+      hist.run = ++run;
+      if (from_policy) {
+        lam = step;  // the plain rule continues from the learned step after a fallback
+      } else if (run >= p.expand_after) {
         lam = std::min(lam * p.expand, p.lambda_max);
         run = 0;
+        hist.run = 0;
       }
     } else {
-      lam *= p.shrink;  // step back: keep (x, t)
+      lam = (from_policy ? step : lam) * p.shrink;  // step back: keep (x, t)
       run = 0;
+      hist.run = 0;
     }
     stop = lam < p.lambda_min || corr >= p.max_steps;
+    (void)blend;
   }
   stats->end_success = 0;
   if (t >= 1.0) {
@@ -617,6 +761,10 @@ extern "C" qdp_status qdp_track_path(const qdp_homotopy *hc, double *x, qdp_prec
   stats->avg_step = succ ? sum_step / (double)succ : 0.0;
   stats->min_step = succ ? min_step : 0.0;
   stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  stats->policy_used = used;
+  stats->policy_rejected = rejected;
+  stats->log_count = nlog;
+  stats->probe_corrections = probes;
   return QDP_OK;
 }
 

@@ -60,6 +60,8 @@ struct NewtonState {
   double refine_err; // mixed precision: last ||correction||_inf / ||dz||_inf
   int refine_steps;  // mixed precision: refinements done in the last solve
   int pad;
+  double dz_first;   // ||dz||_inf of the first iteration
+  double xnorm;      // ||x||_inf after the last update
 };
 
 // launchers (defined per translation unit; return hipError_t)

@@ -286,9 +286,13 @@ __device__ double residual_of(const double *bcol, size_t PS, int n, const double
 }
 
 __device__ inline void newton_bookkeeping(NewtonState *s, double rho, bool singular, bool bad, double dmax,
-                                          double pmax, double pmin) {
+                                          double pmax, double pmin, double xmax) {
   s->iterations += 1;
-  if (s->iterations == 1) s->rho_first = rho;
+  if (s->iterations == 1) {
+    s->rho_first = rho;
+    s->dz_first = dmax;
+  }
+  s->xnorm = xmax;
   s->rho = rho;
   s->dz_norm = dmax;
   s->cond_est = (pmin > 0.0 && pmin < __builtin_inf()) ? pmax / pmin : __builtin_inf();
@@ -338,20 +342,23 @@ __global__ __launch_bounds__(NT) void k_ge(GeArgs<L> a) {
     back_substitute<L>(M, PS, n, el.perm, el.invp, bb,
                        [&](int i) { return pload<L>(M + (size_t)n * n + el.perm[i], PS); });
   __syncthreads();
-  double dmax = 0.0;
+  double dmax = 0.0, xmax = 0.0;
   if (ok) {
     for (int v = tid; v < n; v += NT) {
       const C<L> d = pload<L>(bb + v, n);
       if (a.dz) cstore<L>(a.dz + (size_t)v * E2, d);
       if (a.x) {
         double *xp = a.x + (size_t)v * E2;
-        cstore<L>(xp, cadd<L>(cload<L>(xp), d));
+        const C<L> xn = cadd<L>(cload<L>(xp), d);
+        cstore<L>(xp, xn);
+        xmax = fmax(xmax, cabs1_hi<L>(xn));
       }
       dmax = fmax(dmax, cabs1_hi<L>(d));
     }
   }
   dmax = block_max<NT>(dmax, redbuf);
-  if (tid == 0 && a.st) newton_bookkeeping(a.st, rho, !ok, bad, dmax, pmax, pmin);
+  xmax = block_max<NT>(xmax, redbuf);
+  if (tid == 0 && a.st) newton_bookkeeping(a.st, rho, !ok, bad, dmax, pmax, pmin, xmax);
 }
 
 }  // namespace qdp

@@ -150,17 +150,20 @@ __global__ __launch_bounds__(NT) void k_mixed(MixedArgs a) {
   }
 
   // ---- update and bookkeeping
-  double dmax = 0.0;
+  double dmax = 0.0, xmax = 0.0;
   if (ok)
     for (int v = tid; v < n; v += NT) {
       const C<2> d = pload<2>(dz + v, n);
       double *xp = a.x + (size_t)v * 4;
-      cstore<2>(xp, cadd<2>(cload<2>(xp), d));
+      const C<2> xn = cadd<2>(cload<2>(xp), d);
+      cstore<2>(xp, xn);
       dmax = fmax(dmax, cabs1_hi<2>(d));
+      xmax = fmax(xmax, cabs1_hi<2>(xn));
     }
   dmax = block_max<NT>(dmax, redbuf);
+  xmax = block_max<NT>(xmax, redbuf);
   if (tid == 0 && a.st) {
-    newton_bookkeeping(a.st, rho, !ok, bad, dmax, pmax, pmin);
+    newton_bookkeeping(a.st, rho, !ok, bad, dmax, pmax, pmin, xmax);
     a.st->refine_steps = steps;
     a.st->refine_err = rel;
   }

@@ -23,6 +23,8 @@ __global__ void k_init_state(NewtonState *s, double eps, int max_it) {
   s->refine_err = 0.0;
   s->refine_steps = 0;
   s->pad = 0;
+  s->dz_first = 0.0;
+  s->xnorm = 0.0;
   s->active = (1.0 > eps && max_it > 0) ? 1 : 0;
 }
 
@@ -31,28 +33,82 @@ hipError_t launch_init_state(NewtonState *st, double eps, int max_it, hipStream_
   return hipGetLastError();
 }
 
-// Secant predictor: z' = z + r (z - z_prev) with r = (t' - t)/(t - t_prev);
-// constant predictor (z' = z) before the second accepted point.
+// Secant predictor: z' = z + w r (z - z_prev) with r = (t' - t)/(t - t_prev)
+// (w = 1 is the secant through the last two accepted points; a learned
+// controller may blend it towards the constant predictor w = 0); constant
+// predictor before the second accepted point.  One workgroup; aux[0] gets
+// ||z' - z||_inf (|Re| + |Im| of the leading limbs).
 template <int L>
-__global__ void k_predict(int n, const double *x, const double *xp, double r, int have_prev, double *out) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  const C<L> z = cload<L>(x + (size_t)v * 2 * L);
-  C<L> o = z;
-  if (have_prev) {
-    const C<L> zp = cload<L>(xp + (size_t)v * 2 * L);
-    o = cadd<L>(z, cmul_d<L>(csub<L>(z, zp), r));
+__global__ __launch_bounds__(256) void k_predict(int n, const double *x, const double *xp, double r, int have_prev,
+                                                 double *out, double *aux) {
+  __shared__ double red[4];
+  double m = 0.0;
+  for (int v = threadIdx.x; v < n; v += 256) {
+    const C<L> z = cload<L>(x + (size_t)v * 2 * L);
+    C<L> o = z;
+    if (have_prev) {
+      const C<L> d = cmul_d<L>(csub<L>(z, cload<L>(xp + (size_t)v * 2 * L)), r);
+      o = cadd<L>(z, d);
+      m = fmax(m, cabs1_hi<L>(d));
+    }
+    cstore<L>(out + (size_t)v * 2 * L, o);
   }
-  cstore<L>(out + (size_t)v * 2 * L, o);
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0 && aux) aux[0] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
 hipError_t launch_predict(int L, int n, const double *x, const double *xprev, double r, int have_prev,
-                          double *xpred, hipStream_t s) {
-  dim3 g((n + 255) / 256), b(256);
+                          double *xpred, double *aux, hipStream_t s) {
+  dim3 g(1), b(256);
   switch (L) {
-    case 1: hipLaunchKernelGGL(k_predict<1>, g, b, 0, s, n, x, xprev, r, have_prev, xpred); break;
-    case 2: hipLaunchKernelGGL(k_predict<2>, g, b, 0, s, n, x, xprev, r, have_prev, xpred); break;
-    case 4: hipLaunchKernelGGL(k_predict<4>, g, b, 0, s, n, x, xprev, r, have_prev, xpred); break;
+    case 1: hipLaunchKernelGGL(k_predict<1>, g, b, 0, s, n, x, xprev, r, have_prev, xpred, aux); break;
+    case 2: hipLaunchKernelGGL(k_predict<2>, g, b, 0, s, n, x, xprev, r, have_prev, xpred, aux); break;
+    case 4: hipLaunchKernelGGL(k_predict<4>, g, b, 0, s, n, x, xprev, r, have_prev, xpred, aux); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Best secant weight for a corrected point: with d = z - z_prev and
+// e = z_corr - z, aux[1] = Re <d, e> and aux[2] = <d, d> (leading limbs, fixed
+// order), so that w* = aux[1] / (r aux[2]) minimises |z + w r d - z_corr|.
+template <int L>
+__global__ __launch_bounds__(256) void k_blend_label(int n, const double *x, const double *xp, const double *xc,
+                                                     double *aux) {
+  __shared__ double ra[256], rb[256];
+  double a = 0.0, b = 0.0;
+  for (int v = threadIdx.x; v < n; v += 256) {
+    const C<L> z = cload<L>(x + (size_t)v * 2 * L);
+    const C<L> d = csub<L>(z, cload<L>(xp + (size_t)v * 2 * L));
+    const C<L> e = csub<L>(cload<L>(xc + (size_t)v * 2 * L), z);
+    const double dr = d.re.v[0], di = d.im.v[0], er = e.re.v[0], ei = e.im.v[0];
+    a += dr * er + di * ei;
+    b += dr * dr + di * di;
+  }
+  ra[threadIdx.x] = a;
+  rb[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      ra[threadIdx.x] += ra[threadIdx.x + w];
+      rb[threadIdx.x] += rb[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    aux[1] = ra[0];
+    aux[2] = rb[0];
+  }
+}
+
+hipError_t launch_blend_label(int L, int n, const double *x, const double *xprev, const double *xcorr, double *aux,
+                              hipStream_t s) {
+  switch (L) {
+    case 1: hipLaunchKernelGGL(k_blend_label<1>, dim3(1), dim3(256), 0, s, n, x, xprev, xcorr, aux); break;
+    case 2: hipLaunchKernelGGL(k_blend_label<2>, dim3(1), dim3(256), 0, s, n, x, xprev, xcorr, aux); break;
+    case 4: hipLaunchKernelGGL(k_blend_label<4>, dim3(1), dim3(256), 0, s, n, x, xprev, xcorr, aux); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -32,12 +32,22 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ZSS_LIMBS = 8  # 424 bits: far below the quad-double unit roundoff
 
 
-def fixture_for(sysm, name: str, meta: dict) -> dict:
+def fixture_for(sysm, name: str, meta: dict, refine: bool = True) -> dict:
+    """``refine=False`` skips the high-precision z** (training systems only
+    need the start root); the FP64 target root then comes from an FP64 Newton
+    polish of the planted point."""
     t0 = time.time()
-    rr = refine_root(sysm, sysm.zstar)
-    t_ref = time.time() - t0
     H = F64Homotopy(sysm)
-    zss64 = np.array([complex(v) for v in rr.z])
+    if refine:
+        rr = refine_root(sysm, sysm.zstar)
+        zss64 = np.array([complex(v) for v in rr.z])
+    else:
+        rr = None
+        zss64 = sysm.zstar[:, 0, 0] + 1j * sysm.zstar[:, 1, 0]
+        for _ in range(4):
+            h, J, _ = H.eval(zss64, 1.0)
+            zss64 = zss64 + np.linalg.solve(J, -h)
+    t_ref = time.time() - t0
     k, x0 = start_root_index(H, zss64)
     start = np.exp(2j * np.pi * k / H.deg)
     x_half, _ = track_f64(H, start, 0.0, 0.5)
@@ -45,7 +55,7 @@ def fixture_for(sysm, name: str, meta: dict) -> dict:
     fwd_err = float(np.max(np.abs(x1 - zss64)))
     if fwd_err > 1e-8:
         raise RuntimeError(f"{name}: forward FP64 track missed z** by {fwd_err}")
-    zss = [to_limbs_complex(v, ZSS_LIMBS).tolist() for v in rr.z]
+    zss = [to_limbs_complex(v, ZSS_LIMBS).tolist() for v in rr.z] if refine else None
     out = dict(meta)
     out.update(
         {
@@ -56,7 +66,7 @@ def fixture_for(sysm, name: str, meta: dict) -> dict:
             "degrees": [int(d) for d in H.deg],
             "start_k": [int(v) for v in k],
             "zss_limbs": zss,
-            "refine_corrections": rr.corrections,
+            "refine_corrections": rr.corrections if refine else None,
             "fp64_forward_steps": int(nsteps),
             "fp64_forward_err": fwd_err,
             "x_half_f64": [[float(v.real), float(v.imag)] for v in x_half],
@@ -79,13 +89,13 @@ def main(names):
         print(name, "k[:4] =", out["start_k"][:4], "seconds", round(out["seconds"], 1), flush=True)
 
 
-def main_family(prefix: str, n: int, m: int, E: int, L: int, seeds):
+def main_family(prefix: str, n: int, m: int, E: int, L: int, seeds, refine: bool):
     """Fixtures for a family of systems (learned step control): one JSON with all of them."""
     rows = []
     for seed in seeds:
         s = make_system(n, m, E, L, seed)
         try:
-            out = fixture_for(s, f"{prefix}_{seed}", {"seed": seed, "m": m, "E": E})
+            out = fixture_for(s, f"{prefix}_{seed}", {"seed": seed, "m": m, "E": E}, refine=refine)
         except RuntimeError as e:  # keep going; the family records which seeds failed
             print("skip", seed, e, flush=True)
             continue
@@ -98,8 +108,9 @@ def main_family(prefix: str, n: int, m: int, E: int, L: int, seeds):
 
 if __name__ == "__main__":
     if len(sys.argv) > 1 and sys.argv[1] == "family":
-        # family <prefix> <first_seed> <count>
+        # family <prefix> <first_seed> <count> <refine 0|1>: n=32 systems shaped like the n32 workload
         prefix, first, count = sys.argv[2], int(sys.argv[3]), int(sys.argv[4])
-        main_family(prefix, 32, 32, 3, 2, range(first, first + count))
+        refine = len(sys.argv) > 5 and sys.argv[5] == "1"
+        main_family(prefix, 32, 32, 3, 2, range(first, first + count), refine)
     else:
         main(sys.argv[1:] or ["n8_dd", "n32_dd", "n64_qd", "n64_dd", "n128_dd"])

@@ -1,0 +1,46 @@
+"""Learned step control on held-out systems: what the trained network gains
+over the plain step-size control, with the Newton test as judge."""
+
+import os
+
+import numpy as np
+import pytest
+
+from tests.gpu_helpers import say
+
+pytestmark = pytest.mark.gpu
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_learned_control_beats_plain_on_held_out_systems():
+    from paper_1109_0545_amd import policy
+
+    say("learned vs plain on 10 held-out n=32 systems")
+    r = policy.evaluate(os.path.join(ROOT, "tests", "golden", "family_heldout.json"),
+                        os.path.join(ROOT, "paper_1109_0545_amd", "policy_n32.npz"), limit=10)
+    s = r["summary"]
+    wins = sum(1 for row in r["rows"] if row["learned"]["corrections"] < row["plain"]["corrections"])
+    assert s["plain_fails"] == 0 and s["learned_fails"] == 0
+    assert s["learned_min_digits"] >= 28 and s["plain_min_digits"] >= 28
+    assert s["learned_mean_corrections"] < s["plain_mean_corrections"]
+    assert wins >= 8, r["rows"]
+
+
+def test_learned_control_falls_back_when_the_network_is_wrong():
+    # a network whose logits say "every multiplier fails" proposes 2^-1 steps;
+    # paths still end at the same point (the Newton test judges every step)
+    import paper_1109_0545_amd as q
+    from paper_1109_0545_amd import policy
+    from synth.policy import init_params
+
+    fam = os.path.join(ROOT, "tests", "golden", "family_heldout.json")
+    seed, S, H, x0, fix = next(policy.family_jobs(fam))
+    params = np.zeros_like(init_params(1, policy.WIDTHS))
+    # output biases: logits -20 (never accepted), blend weight 1 (secant)
+    params[-policy.WIDTHS[-1]:] = [-20, -20, -20, -20, -20, 1.0]
+    pol = q.Policy(policy.WIDTHS, params, np.zeros(16), np.ones(16))
+    say("learned fallback")
+    p = q.default_track_params(predictor=q.PRED_LEARNED, policy=pol)
+    z, st, _ = q.track_path(H, x0, 2, p)
+    assert st["fail"] == 0 and st["policy_used"] > 0
+    assert policy.correct_digits(z, fix["zss_limbs"]) >= 28
