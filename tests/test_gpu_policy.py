@@ -27,8 +27,10 @@ def test_learned_control_beats_plain_on_held_out_systems():
 
 
 def test_learned_control_falls_back_when_the_network_is_wrong():
-    # a network whose logits say "every multiplier fails" proposes 2^-1 steps;
-    # paths still end at the same point (the Newton test judges every step)
+    # an over-confident network (every multiplier "accepted") proposes the
+    # largest step each time; the Newton test rejects what does not converge,
+    # the plain rule takes over until the next success, and the path still
+    # ends at the same point
     import paper_1109_0545_amd as q
     from paper_1109_0545_amd import policy
     from synth.policy import init_params
@@ -36,11 +38,11 @@ def test_learned_control_falls_back_when_the_network_is_wrong():
     fam = os.path.join(ROOT, "tests", "golden", "family_heldout.json")
     seed, S, H, x0, fix = next(policy.family_jobs(fam))
     params = np.zeros_like(init_params(1, policy.WIDTHS))
-    # output biases: logits -20 (never accepted), blend weight 1 (secant)
-    params[-policy.WIDTHS[-1]:] = [-20, -20, -20, -20, -20, 1.0]
+    # output biases: logits +20 (always accepted), blend weight 1 (secant)
+    params[-policy.WIDTHS[-1]:] = [20, 20, 20, 20, 20, 1.0]
     pol = q.Policy(policy.WIDTHS, params, np.zeros(16), np.ones(16))
     say("learned fallback")
     p = q.default_track_params(predictor=q.PRED_LEARNED, policy=pol)
     z, st, _ = q.track_path(H, x0, 2, p)
-    assert st["fail"] == 0 and st["policy_used"] > 0
+    assert st["fail"] == 0 and st["policy_used"] > 0 and st["policy_rejected"] > 0
     assert policy.correct_digits(z, fix["zss_limbs"]) >= 28
