@@ -181,8 +181,8 @@ typedef struct {
   int64_t max_steps;    /* stop after this many corrections */
   int32_t mode;         /* qdp_solve */
   int32_t probe;        /* data collection: at every accepted state, also try the step multipliers
-                           2^-1..2^3 and log a probe record (kind 1) per state; the path itself
-                           follows the plain rule */
+                           2^-1..2^3 (quadratic predictor) and log a probe record (kind 1) per
+                           state; the path itself follows the plain rule */
   const qdp_policy *policy; /* learned step control (QDP_PRED_LEARNED), else NULL */
   double lambda_max_learned; /* cap of the learned step size (0: 4 * lambda_max) */
   double accept_threshold;   /* smallest acceptance probability a proposed multiplier may have (0: 0.3) */
@@ -231,7 +231,8 @@ typedef struct {
   double cond_est;
   double znorm;      /* ||z||_inf before the step */
   double pred_dist;  /* ||z_pred - z||_inf */
-  double blend_label;/* kind 1: best secant weight for the 2^0 step (NaN when that step failed) */
+  double blend_label;/* kind 1: least-squares weight of the quadratic predictor against the secant for
+                        the 2^0 step (NaN when that step failed or fewer than 3 points exist) */
   float features[QDP_POLICY_FEATURES]; /* the learned controller's inputs in this state */
   int32_t iterations;
   int32_t accepted;
@@ -240,8 +241,10 @@ typedef struct {
 } qdp_step_record;
 
 /* Track one path from t = 0 to t = 1 (Algorithm 3.1): predict (secant
- * predictor: linear extrapolation through the last two accepted points,
- * constant before the second one), correct with Newton at the new t, control
+ * predictor: linear extrapolation through the last two accepted points;
+ * quadratic predictor (Section 5): per coordinate, the parabola through the
+ * last three accepted points evaluated at the new t; before enough points,
+ * the lower-order one, and constant before the second point), correct with Newton at the new t, control
  * the step size (step back and shrink on failure, expand after successes),
  * stop when the step is below lambda_min or after max_steps corrections; at
  * t = 1 refine the endpoint.  fail = (t < 1 at exit).
@@ -249,9 +252,9 @@ typedef struct {
  * network scores the multipliers 2^-1..2^3 of the last accepted step size (acceptance
  * probabilities p_k); the multiplier chosen by policy_rule is tried (capped by
  * lambda_max_learned and 1 - t; 2^-1 when no multiplier qualifies) with the predictor
- * z + w r (z - z_prev), w the network's secant weight in [0, 1.5].  The Newton
- * test judges: a failed correction steps back and falls back to the plain rule
- * (shrink, secant) until the next success.
+ * (1 - w) secant + w quadratic, w the network's last output clamped to [-0.5, 1.5].
+ * The Newton test judges: a failed correction steps back and falls back to the
+ * plain rule (shrink, quadratic predictor) until the next success.
  *   x        : [n][2][prec] in: start solution at t = 0; out: end point
  *   step_log : NULL, or room for log_cap records; records are written in order
  *              (corrector stages, plus probe records in probe mode) until full */

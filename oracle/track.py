@@ -13,11 +13,14 @@ reference tracker loop, and correct decimal places.
   backward path follows from the random-gamma construction of the total
   degree homotopy (a standard fact of homotopy continuation, not stated in
   the paper).
+* ``extrapolate``: the predictor, the interpolating polynomial through the
+  last accepted points evaluated at the next t (two points: the secant
+  predictor; three: the quadratic predictor of Section 5).
 * ``track_reference``: the loop of Algorithm 3.1 (predict, correct with the
   Newton loop of Algorithm 4.1, step size control, step back on failure,
-  stop criterion) in high precision, with the secant predictor.  The paper
-  prints neither the predictor formula nor the step-size constants; the
-  readings used are in ``TrackParams``.
+  stop criterion) in high precision, with the secant or the quadratic
+  predictor.  The paper prints neither the predictor formula nor the
+  step-size constants; the readings used are in ``TrackParams``.
 * ``correct_digits``: the quality Q of Section 2 (number of correct decimal
   places) measured against z**.
 
@@ -26,7 +29,8 @@ in closed form; ``track_reference`` by the closed-form path of a decoupled
 target (every accepted point lies on the branch x_i(t)^(d_i) =
 ((1-t) gamma + t c_i)/((1-t) gamma + t)), by the stationary path f = g, and
 by the invariants (accepted steps sum to 1; corrections >= successes; every
-step on the 0.01 * 2^j grid until the final clamp).
+step on the 0.01 * 2^j grid until the final clamp); ``extrapolate`` by exact
+reproduction of polynomial paths of degree below the number of points.
 """
 
 from __future__ import annotations
@@ -247,6 +251,7 @@ class TrackParams:
     eps_end: float = 0.0  # 0 selects 64 u_L
     max_it_end: int = 10
     max_steps: int = 2_000_000
+    predictor: str = "secant"  # or "quadratic"
 
 
 @dataclasses.dataclass
@@ -259,6 +264,27 @@ class TrackResult:
     newton_iterations: int
     steps: List[float]  # accepted step sizes
     history: List[tuple] = dataclasses.field(default_factory=list)  # accepted (t, z)
+    predictions: List[tuple] = dataclasses.field(default_factory=list)  # every correction: (t, lam, t', z, z')
+
+
+def extrapolate(ts, zs, tn):
+    """Value at ``tn`` of the interpolating polynomial through the points
+    (ts[j], zs[j]) (one coordinate list per point), in Lagrange form:
+    z' = sum_j l_j(tn) z_j with l_j(tn) = prod_{k != j} (tn - t_k)/(t_j - t_k).
+    One point gives the constant predictor, two the secant (linear
+    extrapolation), three the quadratic predictor.  Runs at the caller's
+    working precision."""
+    m = len(ts)
+    T = [mpmath.mpf(v) for v in ts]
+    tn = mpmath.mpf(tn)
+    w = []
+    for j in range(m):
+        lj = mpmath.mpf(1)
+        for k in range(m):
+            if k != j:
+                lj *= (tn - T[k]) / (T[j] - T[k])
+        w.append(lj)
+    return [mpmath.fsum(w[j] * zs[j][v] for j in range(m)) for v in range(len(zs[0]))]
 
 
 def _limbs_point(z: list, L: int) -> np.ndarray:
@@ -269,13 +295,14 @@ def _limbs_point(z: list, L: int) -> np.ndarray:
 
 def track_reference(sys, z0: np.ndarray, p: TrackParams = TrackParams(), round_limbs: bool = True,
                     record: bool = False) -> TrackResult:
-    """Algorithm 3.1 with the secant predictor, in high precision.
+    """Algorithm 3.1 with the secant or the quadratic predictor, in high precision.
 
-    Predictor (reading of the unprinted secant predictor): with the last two
-    accepted points (t_prev, z_prev), (t, z) and the step
+    Predictor (reading of the unprinted predictors): with the step
     lam = min(lambda, 1 - t), predict t' = t + lam (t' = 1 when the step
-    reaches the end) and z' = z + (lam / (t - t_prev)) (z - z_prev); before
-    the second accepted point the predictor is constant (z' = z).
+    reaches the end) and z' = ``extrapolate`` through the last accepted
+    points: two for the secant predictor, i.e. z' = z + (lam / (t - t_prev))
+    (z - z_prev), three for the quadratic one (two while only two exist);
+    before the second accepted point the predictor is constant (z' = z).
     Corrector: the Newton loop of Algorithm 4.1 with eps_path, max_it_path.
     Step size control: on success accept and, after ``expand_after``
     consecutive successes, lambda := min(expand * lambda, lambda_max); on
@@ -294,7 +321,9 @@ def track_reference(sys, z0: np.ndarray, p: TrackParams = TrackParams(), round_l
     with mpmath.workprec(prec):
         z = vec_mpc(z0)
         t = 0.0
-        zp, tp = None, None
+        pts = [(0.0, z)]  # accepted points, newest last, at most the predictor's order + 1
+        order = {"secant": 2, "quadratic": 3}[p.predictor]
+        preds: List[tuple] = []
         lam = p.lambda0
         run = 0
         succ = corr = nit = 0
@@ -304,11 +333,9 @@ def track_reference(sys, z0: np.ndarray, p: TrackParams = TrackParams(), round_l
         while t < 1.0 and not stop:
             step = min(lam, 1.0 - t)
             tn = 1.0 if t + step >= 1.0 else t + step
-            if zp is None:
-                zq = list(z)
-            else:
-                r = mpmath.mpf(tn - t) / mpmath.mpf(t - tp)
-                zq = [a + r * (a - b) for a, b in zip(z, zp)]
+            zq = extrapolate([a for a, _ in pts], [b for _, b in pts], tn)
+            if record:
+                preds.append((t, step, tn, list(z), list(zq)))
             # Newton loop (Algorithm 4.1)
             rho, it = 1.0, 0
             y = zq
@@ -325,8 +352,8 @@ def track_reference(sys, z0: np.ndarray, p: TrackParams = TrackParams(), round_l
             if rho < p.eps_path:
                 if round_limbs:
                     y = vec_mpc(_limbs_point(y, L))
-                zp, tp = z, t
                 z, t = y, tn
+                pts = (pts + [(t, z)])[-order:]
                 succ += 1
                 steps.append(step)
                 if record:
@@ -353,4 +380,4 @@ def track_reference(sys, z0: np.ndarray, p: TrackParams = TrackParams(), round_l
             nit += it
             if round_limbs:
                 z = vec_mpc(_limbs_point(z, L))
-        return TrackResult(z, t, t < 1.0, succ, corr, nit, steps, hist)
+        return TrackResult(z, t, t < 1.0, succ, corr, nit, steps, hist, preds)

@@ -22,10 +22,10 @@ hipError_t launch_ge_scaled(int L, int n, double *ab, double *scale, double *x, 
 hipError_t launch_arith(int op, int L, int64_t count, const double *a, const double *b, const double *c,
                         double *out, hipStream_t s);
 hipError_t launch_init_state(NewtonState *st, double eps, int max_it, hipStream_t s);
-hipError_t launch_predict(int L, int n, const double *x, const double *xprev, double r, int have_prev,
-                          double *xpred, double *aux, hipStream_t s);
-hipError_t launch_blend_label(int L, int n, const double *x, const double *xprev, const double *xcorr, double *aux,
-                              hipStream_t s);
+hipError_t launch_predict(int L, int n, const double *x, const double *xprev, const double *xprev2, double c1,
+                          double c2, double *xpred, double *aux, hipStream_t s);
+hipError_t launch_blend_label(int L, int n, const double *x, const double *xprev, const double *xprev2,
+                              const double *xcorr, double s1, double q1, double q2, double *aux, hipStream_t s);
 hipError_t launch_copy(double *dst, const double *src, size_t count, hipStream_t s);
 hipError_t launch_mixed_solve(int n, double *ab, double *scale, double *x, NewtonState *st, double *lu,
                               double *work, int refinements, hipStream_t s);
@@ -79,6 +79,7 @@ struct Workspace {
   double *scale = nullptr;  // [n]
   double *x = nullptr;      // [n] point (compute precision)
   double *xprev = nullptr;  // [n] previous accepted point
+  double *xprev2 = nullptr; // [n] the accepted point before that
   double *xw = nullptr;     // [n] working point (predicted / corrected)
   double *y = nullptr;      // [n] values (eval entry points)
   double *jac = nullptr;    // [n][n] Jacobian (eval entry points)
@@ -108,6 +109,7 @@ static qdp_status ensure_ws(qdp_homotopy *h, int L, Workspace **out) {
     HIPCHK(hipMalloc(&w.scale, (size_t)n * sizeof(double)));
     HIPCHK(hipMalloc(&w.x, (size_t)n * e * sizeof(double)));
     HIPCHK(hipMalloc(&w.xprev, (size_t)n * e * sizeof(double)));
+    HIPCHK(hipMalloc(&w.xprev2, (size_t)n * e * sizeof(double)));
     HIPCHK(hipMalloc(&w.xw, (size_t)n * e * sizeof(double)));
     HIPCHK(hipMalloc(&w.y, (size_t)n * e * sizeof(double)));
     HIPCHK(hipMalloc(&w.jac, (size_t)n * n * e * sizeof(double)));
@@ -128,6 +130,7 @@ static void free_ws(Workspace &w) {
   hipFree(w.scale);
   hipFree(w.x);
   hipFree(w.xprev);
+  hipFree(w.xprev2);
   hipFree(w.xw);
   hipFree(w.y);
   hipFree(w.jac);
@@ -562,10 +565,12 @@ extern "C" qdp_status qdp_track_path(const qdp_homotopy *hc, double *x, qdp_prec
   if (p.mode != QDP_SOLVE_FULL && p.mode != QDP_SOLVE_MIXED_IR) return fail(QDP_EINVAL, "bad solve mode");
   if (p.mode == QDP_SOLVE_MIXED_IR && L != 2)
     return fail(QDP_EUNSUPPORTED, "mixed-precision refinement is implemented for double double");
-  if (p.predictor == QDP_PRED_QUADRATIC) return fail(QDP_EUNSUPPORTED, "quadratic predictor not built");
   const bool learned = p.predictor == QDP_PRED_LEARNED;
   if (learned && !p.policy) return fail(QDP_EINVAL, "learned predictor needs a policy");
-  if (p.predictor != QDP_PRED_SECANT && !learned) return fail(QDP_EINVAL, "unknown predictor");
+  if (p.predictor != QDP_PRED_SECANT && p.predictor != QDP_PRED_QUADRATIC && !learned)
+    return fail(QDP_EINVAL, "unknown predictor");
+  // quadratic weight of the plain predictor; the learned controller falls back to the quadratic one
+  const double plain_wq = p.predictor == QDP_PRED_SECANT ? 0.0 : 1.0;
   const double lam_cap = learned ? (p.lambda_max_learned > 0 ? p.lambda_max_learned : 4 * p.lambda_max) : p.lambda_max;
   const double thr = p.accept_threshold > 0 ? p.accept_threshold : 0.3;
   if (thr >= 1.0) return fail(QDP_EINVAL, "accept_threshold must be below 1");
@@ -583,8 +588,9 @@ extern "C" qdp_status qdp_track_path(const qdp_homotopy *hc, double *x, qdp_prec
   HIPCHK(hipMemcpyAsync(w->x, x, bytes, hipMemcpyHostToDevice, st));
 
   std::memset(stats, 0, sizeof(*stats));
-  double t = 0.0, tprev = 0.0, lam = p.lambda0, blend = 1.0;
-  bool have_prev = false, stop = false, from_policy = false;
+  double t = 0.0, tprev = 0.0, tprev2 = 0.0, lam = p.lambda0;
+  int npts = 1;  // accepted points available to the predictor (1, 2, 3 = three or more)
+  bool stop = false, from_policy = false;
   int run = 0;
   int64_t succ = 0, corr = 0, nit = 0, nlog = 0, used = 0, rejected = 0, probes = 0;
   double sum_step = 0.0, min_step = INFINITY;
@@ -595,12 +601,28 @@ extern "C" qdp_status qdp_track_path(const qdp_homotopy *hc, double *x, qdp_prec
   auto push = [&](const qdp_step_record &r) {
     if (log && nlog < log_cap) log[nlog++] = r;
   };
-  // one corrector stage from the current accepted point with step `step` and secant weight `wgt`
-  auto correct = [&](double step, double wgt, double &tn_out) -> qdp_status {
+  // predictor coefficients at tn: secant s1, quadratic (q1, q2) (see k_predict)
+  auto coefs = [&](double tn, double &s1, double &q1, double &q2) {
+    s1 = npts >= 2 ? -(tn - t) / (t - tprev) : 0.0;
+    q1 = q2 = 0.0;
+    if (npts >= 3) {
+      q1 = ((tn - t) * (tn - tprev2)) / ((tprev - t) * (tprev - tprev2));
+      q2 = ((tn - t) * (tn - tprev)) / ((tprev2 - t) * (tprev2 - tprev));
+    }
+  };
+  // one corrector stage from the current accepted point with step `step`;
+  // wq weights the quadratic predictor against the secant (0 = secant)
+  auto correct = [&](double step, double wq, double &tn_out) -> qdp_status {
     const double tn = (t + step >= 1.0) ? 1.0 : t + step;
     tn_out = tn;
-    const double r = have_prev ? wgt * (tn - t) / (t - tprev) : 0.0;
-    HIPCHK(qdp::launch_predict(L, n, w->x, w->xprev, r, have_prev ? 1 : 0, w->xw, w->aux, st));
+    double s1, q1, q2;
+    coefs(tn, s1, q1, q2);
+    double c1 = s1, c2 = 0.0;
+    if (npts >= 3) {
+      c1 = (1.0 - wq) * s1 + wq * q1;
+      c2 = wq * q2;
+    }
+    HIPCHK(qdp::launch_predict(L, n, w->x, w->xprev, w->xprev2, c1, c2, w->xw, w->aux, st));
     qdp_status e = enqueue_newton(h, w, L, tn, w->xw, p.mode, p.eps_path, p.max_it_path, st);
     if (e != QDP_OK) return e;
     HIPCHK(hipMemcpyAsync(&ns, w->st, sizeof(ns), hipMemcpyDeviceToHost, st));
@@ -611,7 +633,7 @@ extern "C" qdp_status qdp_track_path(const qdp_homotopy *hc, double *x, qdp_prec
 
   while (t < 1.0 && !stop) {
     // ---- probes (data collection): all multipliers from this accepted state
-    if (p.probe && have_prev) {
+    if (p.probe && npts >= 2) {
       qdp_step_record rec;
       std::memset(&rec, 0, sizeof(rec));
       rec.kind = 1;
@@ -626,12 +648,13 @@ extern "C" qdp_status qdp_track_path(const qdp_homotopy *hc, double *x, qdp_prec
         ++probes;
         if (ns.success) {
           rec.probe_ok |= 1 << k;
-          if (k == 1) {
-            HIPCHK(qdp::launch_blend_label(L, n, w->x, w->xprev, w->xw, w->aux, st));
+          if (k == 1 && npts >= 3) {
+            double s1, q1, q2;
+            coefs(tn, s1, q1, q2);
+            HIPCHK(qdp::launch_blend_label(L, n, w->x, w->xprev, w->xprev2, w->xw, s1, q1, q2, w->aux, st));
             HIPCHK(hipMemcpyAsync(aux, w->aux, sizeof(aux), hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
-            const double r = (tn - t) / (t - tprev);
-            if (aux[2] > 0) rec.blend_label = aux[1] / (r * aux[2]);
+            if (aux[2] > 0) rec.blend_label = aux[1] / aux[2];
           }
         }
       }
@@ -639,9 +662,9 @@ extern "C" qdp_status qdp_track_path(const qdp_homotopy *hc, double *x, qdp_prec
     }
     // ---- choose the step
     double step = std::min(lam, 1.0 - t);
-    double wgt = 1.0;
+    double wgt = plain_wq;
     from_policy = false;
-    if (learned && have_prev && run > 0) {
+    if (learned && npts >= 2 && run > 0) {
       // after a success: the network proposes the multiplier and the secant weight
       features(hist, t, feat);
       float out[8];
@@ -660,7 +683,7 @@ extern "C" qdp_status qdp_track_path(const qdp_homotopy *hc, double *x, qdp_prec
       const double mult = best >= 0 ? std::ldexp(1.0, best - 1) : 0.5;
       step = std::min(std::min(hist.lam_acc[0] * mult, lam_cap), 1.0 - t);
       step = std::max(step, std::min(p.lambda_min, 1.0 - t));
-      wgt = std::min(std::max((double)out[5], 0.0), 1.5);
+      wgt = std::min(std::max((double)out[5], -0.5), 1.5);
       from_policy = true;
     }
     double tn;
@@ -693,12 +716,14 @@ extern "C" qdp_status qdp_track_path(const qdp_homotopy *hc, double *x, qdp_prec
       if (!ok) ++rejected;
     }
     if (ok) {
-      // accept: (x_prev, t_prev) <- (x, t); (x, t) <- (corrected, tn)
+      // accept: (x_prev2, x_prev, x) <- (x_prev, x, corrected), same for t
+      std::swap(w->xprev2, w->xprev);
       std::swap(w->xprev, w->x);
       std::swap(w->x, w->xw);
+      tprev2 = tprev;
       tprev = t;
       t = tn;
-      have_prev = true;
+      npts = std::min(npts + 1, 3);
       ++succ;
       sum_step += step;
       min_step = std::min(min_step, step);
@@ -727,7 +752,6 @@ extern "C" qdp_status qdp_track_path(const qdp_homotopy *hc, double *x, qdp_prec
       hist.run = 0;
     }
     stop = lam < p.lambda_min || corr >= p.max_steps;
-    (void)blend;
   }
   stats->end_success = 0;
   if (t >= 1.0) {

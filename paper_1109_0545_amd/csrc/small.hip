@@ -33,25 +33,29 @@ hipError_t launch_init_state(NewtonState *st, double eps, int max_it, hipStream_
   return hipGetLastError();
 }
 
-// Secant predictor: z' = z + w r (z - z_prev) with r = (t' - t)/(t - t_prev)
-// (w = 1 is the secant through the last two accepted points; a learned
-// controller may blend it towards the constant predictor w = 0); constant
-// predictor before the second accepted point.  One workgroup; aux[0] gets
-// ||z' - z||_inf (|Re| + |Im| of the leading limbs).
+// Predictor: z' = z + c1 (z_prev - z) + c2 (z_prev2 - z), the coefficients
+// formed on the host in FP64 from the parameter values:
+//   constant   (one accepted point):   c1 = c2 = 0;
+//   secant     (two points):           c1 = -(t' - t)/(t - t_prev), c2 = 0
+//              (linear extrapolation through the last two accepted points);
+//   quadratic  (three points, Section 5): c1, c2 the Lagrange weights of the
+//              parabola through (t_prev2, z_prev2), (t_prev, z_prev), (t, z)
+//              evaluated at t', coordinate by coordinate;
+//   blends of the secant and quadratic coefficients (learned controller).
+// Writing z' as z plus weighted differences keeps the small increments
+// accurate.  One workgroup; aux[0] gets ||z' - z||_inf (leading limbs).
 template <int L>
-__global__ __launch_bounds__(256) void k_predict(int n, const double *x, const double *xp, double r, int have_prev,
-                                                 double *out, double *aux) {
+__global__ __launch_bounds__(256) void k_predict(int n, const double *x, const double *xp, const double *xpp,
+                                                 double c1, double c2, double *out, double *aux) {
   __shared__ double red[4];
   double m = 0.0;
   for (int v = threadIdx.x; v < n; v += 256) {
     const C<L> z = cload<L>(x + (size_t)v * 2 * L);
-    C<L> o = z;
-    if (have_prev) {
-      const C<L> d = cmul_d<L>(csub<L>(z, cload<L>(xp + (size_t)v * 2 * L)), r);
-      o = cadd<L>(z, d);
-      m = fmax(m, cabs1_hi<L>(d));
-    }
-    cstore<L>(out + (size_t)v * 2 * L, o);
+    C<L> d = czero<L>();
+    if (c1 != 0.0) d = cmul_d<L>(csub<L>(cload<L>(xp + (size_t)v * 2 * L), z), c1);
+    if (c2 != 0.0) d = cadd<L>(d, cmul_d<L>(csub<L>(cload<L>(xpp + (size_t)v * 2 * L), z), c2));
+    cstore<L>(out + (size_t)v * 2 * L, cadd<L>(z, d));
+    m = fmax(m, cabs1_hi<L>(d));
   }
   for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
@@ -59,30 +63,35 @@ __global__ __launch_bounds__(256) void k_predict(int n, const double *x, const d
   if (threadIdx.x == 0 && aux) aux[0] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
-hipError_t launch_predict(int L, int n, const double *x, const double *xprev, double r, int have_prev,
-                          double *xpred, double *aux, hipStream_t s) {
+hipError_t launch_predict(int L, int n, const double *x, const double *xprev, const double *xprev2, double c1,
+                          double c2, double *xpred, double *aux, hipStream_t s) {
   dim3 g(1), b(256);
   switch (L) {
-    case 1: hipLaunchKernelGGL(k_predict<1>, g, b, 0, s, n, x, xprev, r, have_prev, xpred, aux); break;
-    case 2: hipLaunchKernelGGL(k_predict<2>, g, b, 0, s, n, x, xprev, r, have_prev, xpred, aux); break;
-    case 4: hipLaunchKernelGGL(k_predict<4>, g, b, 0, s, n, x, xprev, r, have_prev, xpred, aux); break;
+    case 1: hipLaunchKernelGGL(k_predict<1>, g, b, 0, s, n, x, xprev, xprev2, c1, c2, xpred, aux); break;
+    case 2: hipLaunchKernelGGL(k_predict<2>, g, b, 0, s, n, x, xprev, xprev2, c1, c2, xpred, aux); break;
+    case 4: hipLaunchKernelGGL(k_predict<4>, g, b, 0, s, n, x, xprev, xprev2, c1, c2, xpred, aux); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-// Best secant weight for a corrected point: with d = z - z_prev and
-// e = z_corr - z, aux[1] = Re <d, e> and aux[2] = <d, d> (leading limbs, fixed
-// order), so that w* = aux[1] / (r aux[2]) minimises |z + w r d - z_corr|.
+// Least-squares weight of the quadratic term for a corrected point: with the
+// secant prediction z_s and the quadratic prediction z_q (coefficients as in
+// k_predict) and d = z_q - z_s, e = z_corr - z_s: aux[1] = Re <d, e>,
+// aux[2] = <d, d> (leading limbs, fixed order), so w* = aux[1]/aux[2]
+// minimises |z_s + w d - z_corr|.
 template <int L>
-__global__ __launch_bounds__(256) void k_blend_label(int n, const double *x, const double *xp, const double *xc,
+__global__ __launch_bounds__(256) void k_blend_label(int n, const double *x, const double *xp, const double *xpp,
+                                                     const double *xc, double s1, double q1, double q2,
                                                      double *aux) {
   __shared__ double ra[256], rb[256];
   double a = 0.0, b = 0.0;
   for (int v = threadIdx.x; v < n; v += 256) {
     const C<L> z = cload<L>(x + (size_t)v * 2 * L);
-    const C<L> d = csub<L>(z, cload<L>(xp + (size_t)v * 2 * L));
-    const C<L> e = csub<L>(cload<L>(xc + (size_t)v * 2 * L), z);
+    const C<L> dp = csub<L>(cload<L>(xp + (size_t)v * 2 * L), z);
+    const C<L> dpp = csub<L>(cload<L>(xpp + (size_t)v * 2 * L), z);
+    const C<L> d = cadd<L>(cmul_d<L>(dp, q1 - s1), cmul_d<L>(dpp, q2));
+    const C<L> e = csub<L>(csub<L>(cload<L>(xc + (size_t)v * 2 * L), z), cmul_d<L>(dp, s1));
     const double dr = d.re.v[0], di = d.im.v[0], er = e.re.v[0], ei = e.im.v[0];
     a += dr * er + di * ei;
     b += dr * dr + di * di;
@@ -103,12 +112,13 @@ __global__ __launch_bounds__(256) void k_blend_label(int n, const double *x, con
   }
 }
 
-hipError_t launch_blend_label(int L, int n, const double *x, const double *xprev, const double *xcorr, double *aux,
-                              hipStream_t s) {
+hipError_t launch_blend_label(int L, int n, const double *x, const double *xprev, const double *xprev2,
+                              const double *xcorr, double s1, double q1, double q2, double *aux, hipStream_t s) {
+  dim3 g(1), b(256);
   switch (L) {
-    case 1: hipLaunchKernelGGL(k_blend_label<1>, dim3(1), dim3(256), 0, s, n, x, xprev, xcorr, aux); break;
-    case 2: hipLaunchKernelGGL(k_blend_label<2>, dim3(1), dim3(256), 0, s, n, x, xprev, xcorr, aux); break;
-    case 4: hipLaunchKernelGGL(k_blend_label<4>, dim3(1), dim3(256), 0, s, n, x, xprev, xcorr, aux); break;
+    case 1: hipLaunchKernelGGL(k_blend_label<1>, g, b, 0, s, n, x, xprev, xprev2, xcorr, s1, q1, q2, aux); break;
+    case 2: hipLaunchKernelGGL(k_blend_label<2>, g, b, 0, s, n, x, xprev, xprev2, xcorr, s1, q1, q2, aux); break;
+    case 4: hipLaunchKernelGGL(k_blend_label<4>, g, b, 0, s, n, x, xprev, xprev2, xcorr, s1, q1, q2, aux); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

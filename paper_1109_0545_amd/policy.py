@@ -5,12 +5,13 @@ with ``probe = 1``), training (``qdp_policy_train_step``: the FP32 forward,
 backward and Adam kernels) and inference (BF16 kernel inside the tracker).
 This module only assembles batches and reports.
 
-Data: at every accepted state of a plain (secant) path, the tracker tries the
-step multipliers 2^-1, 2^0, 2^1, 2^2, 2^3 of the last accepted step and
-records which ones the Newton test accepts, plus the least-squares secant
-weight of the 2^0 step (``qdp_step_record`` of kind 1).  Targets: the five
-accept flags (binary cross-entropy) and the secant weight (squared error,
-masked when unavailable or outside [-1, 3]).
+Data: at every accepted state of a plain path (quadratic predictor), the
+tracker tries the step multipliers 2^-1, 2^0, 2^1, 2^2, 2^3 of the last
+accepted step and records which ones the Newton test accepts, plus the
+least-squares weight of the quadratic predictor against the secant for the
+2^0 step (``qdp_step_record`` of kind 1).  Targets: the five accept flags
+(binary cross-entropy) and that weight (squared error, masked when
+unavailable or outside [-1, 3]).
 
 Command line (n = 32 systems described by a family file of seeds and start
 roots):
@@ -74,7 +75,7 @@ def records_to_dataset(recs: List[dict]):
 def collect(family: str, out: str, log_cap: int = 40000) -> Dict:
     Xs, Ys, Ms = [], [], []
     t0 = time.time()
-    params = B.default_track_params(probe=1)
+    params = B.default_track_params(probe=1, predictor=B.PRED_QUADRATIC)
     for seed, S, H, x0, _ in family_jobs(family):
         _, st, recs = B.track_path(H, x0, 2, params, log_cap=log_cap)
         X, Y, M = records_to_dataset(recs)
@@ -147,41 +148,44 @@ def evaluate(family: str, policy_path: str, limit: int = 0, rule: int = 0, thres
              cap: float = 0.32) -> Dict:
     pol = load(policy_path)
     plain = B.default_track_params()
+    plain_q = B.default_track_params(predictor=B.PRED_QUADRATIC)
     learned = B.default_track_params(predictor=B.PRED_LEARNED, policy=pol, policy_rule=rule,
                                      accept_threshold=threshold, lambda_max_learned=cap)
     rows = []
     for i, (seed, S, H, x0, fix) in enumerate(family_jobs(family)):
         if limit and i >= limit:
             break
-        zp, sp, _ = B.track_path(H, x0, 2, plain)
+        row = {"seed": seed}
+        for key, prm in (("plain", plain), ("plain_quadratic", plain_q)):
+            zp, sp, _ = B.track_path(H, x0, 2, prm)
+            row[key] = {"corrections": sp["corrections"], "succ": sp["succ_corrections"], "seconds": sp["seconds"],
+                        "newton_iterations": sp["newton_iterations"], "fail": sp["fail"],
+                        "digits": correct_digits(zp, fix["zss_limbs"]) if not sp["fail"] else -1}
         zl, sl, _ = B.track_path(H, x0, 2, learned)
-        rows.append({
-            "seed": seed,
-            "plain": {"corrections": sp["corrections"], "succ": sp["succ_corrections"], "seconds": sp["seconds"],
-                      "fail": sp["fail"], "digits": correct_digits(zp, fix["zss_limbs"]) if not sp["fail"] else -1},
+        row.update({
             "learned": {"corrections": sl["corrections"], "succ": sl["succ_corrections"], "seconds": sl["seconds"],
-                        "fail": sl["fail"], "policy_used": sl["policy_used"],
-                        "policy_rejected": sl["policy_rejected"],
+                        "newton_iterations": sl["newton_iterations"], "fail": sl["fail"],
+                        "policy_used": sl["policy_used"], "policy_rejected": sl["policy_rejected"],
                         "digits": correct_digits(zl, fix["zss_limbs"]) if not sl["fail"] else -1},
         })
+        rows.append(row)
     def agg(key, f):
         return float(np.mean([r[key][f] for r in rows]))
 
-    summary = {
-        "systems": len(rows),
-        "plain_mean_corrections": agg("plain", "corrections"),
-        "learned_mean_corrections": agg("learned", "corrections"),
-        "plain_median_corrections": float(np.median([r["plain"]["corrections"] for r in rows])),
-        "learned_median_corrections": float(np.median([r["learned"]["corrections"] for r in rows])),
-        "plain_mean_seconds": agg("plain", "seconds"),
-        "learned_mean_seconds": agg("learned", "seconds"),
-        "plain_fails": int(sum(r["plain"]["fail"] for r in rows)),
-        "learned_fails": int(sum(r["learned"]["fail"] for r in rows)),
-        "plain_min_digits": int(min(r["plain"]["digits"] for r in rows)),
-        "learned_min_digits": int(min(r["learned"]["digits"] for r in rows)),
+    summary = {"systems": len(rows)}
+    for key in ("plain", "plain_quadratic", "learned"):
+        summary.update({
+            f"{key}_mean_corrections": agg(key, "corrections"),
+            f"{key}_median_corrections": float(np.median([r[key]["corrections"] for r in rows])),
+            f"{key}_mean_newton_iterations": agg(key, "newton_iterations"),
+            f"{key}_mean_seconds": agg(key, "seconds"),
+            f"{key}_fails": int(sum(r[key]["fail"] for r in rows)),
+            f"{key}_min_digits": int(min(r[key]["digits"] for r in rows)),
+        })
+    summary.update({
         "learned_rejected_fraction": float(sum(r["learned"]["policy_rejected"] for r in rows) /
                                            max(1, sum(r["learned"]["policy_used"] for r in rows))),
-    }
+    })
     summary.update({"rule": rule, "threshold": threshold, "cap": cap})
     return {"summary": summary, "rows": rows}
 

@@ -103,3 +103,46 @@ def test_track_step_log_and_invariants():
         j = math.log2(lam / 0.01)
         assert j == round(j)
     assert st["min_step"] == min(acc)
+
+
+def test_track_quadratic_predictor_endpoints():
+    """The quadratic predictor (Section 5) reaches z** to double-double
+    accuracy and needs no more Newton iterations than the secant predictor."""
+    import paper_1109_0545_amd as q
+
+    for name in ("n8_dd", "n32_dd"):
+        z, st, zss = track_config(name, predictor=q.PRED_QUADRATIC)
+        assert not st["fail"] and st["t_final"] == 1.0
+        assert correct_digits(z, zss) >= 28
+        _, sec, _ = track_config(name)
+        say(name, "newton iterations quadratic", st["newton_iterations"], "secant", sec["newton_iterations"])
+        assert st["newton_iterations"] <= sec["newton_iterations"]
+
+
+def test_track_quadratic_predictions_match_oracle():
+    """Step by step against the oracle tracker on the n = 8 workload: while both
+    take the same steps, the predictor's displacement max_v |z'_v - z_v|
+    (|re| + |im|) agrees with the oracle's interpolant through the last three
+    accepted points (FP64 coefficients on the device: 1e-12 relative)."""
+    import paper_1109_0545_amd as q
+    from oracle.track import TrackParams, track_reference
+
+    fix = fixture("n8_dd")
+    s = config_system(CONFIGS["n8_dd"])
+    S = q.System.from_synth(s)
+    H = q.Homotopy(S, s.gamma)
+    x0 = start_root(np.array(fix["degrees"]), np.array(fix["start_k"]), 2)
+    say("track quadratic log n8")
+    _, st, log = q.track_path(H, x0, 2, q.default_track_params(predictor=q.PRED_QUADRATIC), log_cap=10000)
+    ref = track_reference(s, x0, TrackParams(predictor="quadratic"), record=True)
+    same = 0
+    for rec, (t, lam, tn, z, zq) in zip(log, ref.predictions):
+        # equal states: same t and step (a differing accept decision shows up as a differing t)
+        if rec["t"] != t or rec["lam"] != lam:
+            break
+        with mpmath.workprec(300):
+            d = max(abs(mpmath.re(a - b)) + abs(mpmath.im(a - b)) for a, b in zip(zq, z))
+        assert abs(rec["pred_dist"] - d) <= 1e-12 * d, (same, rec["pred_dist"], d)
+        same += 1
+    say("steps compared", same, "of", len(log), "oracle", len(ref.predictions))
+    assert same >= min(30, len(ref.predictions))

@@ -10,10 +10,10 @@ import mpmath
 import numpy as np
 import pytest
 
-from oracle.numbers import mpc_of, vec_mpc
+from oracle.numbers import mpc_of, prec_bits, vec_mpc
 from oracle.quality import cores_for_equal_time, quality_up_estimate, speedup
-from oracle.track import F64Homotopy, TrackParams, correct_digits, refine_root, start_root_index, track_f64, \
-    track_reference
+from oracle.track import F64Homotopy, TrackParams, correct_digits, extrapolate, refine_root, start_root_index, \
+    track_f64, track_reference
 from synth.systems import CONFIGS, System, config_system, start_root, unit_phasor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -76,6 +76,63 @@ def test_decoupled_target_closed_form_path():
             ref = branch(d[i], k[i], cmath.exp(2j * math.pi * float(c_turns[i])), g, 1.0)
             best = min(roots, key=lambda q: abs(complex(q) - ref))
             assert abs(r.z[i] - best) < mpmath.mpf(10) ** -29
+
+
+def test_extrapolate_reproduces_polynomial_paths():
+    # z(t) = a + b t + c t^2 per coordinate, rational coefficients, exact arithmetic at 400 bits
+    rng = np.random.Generator(np.random.PCG64(11))
+    with mpmath.workprec(400):
+        coef = [[mpmath.mpc(mpmath.mpf(int(rng.integers(-9, 10))) / 7, mpmath.mpf(int(rng.integers(-9, 10))) / 5)
+                 for _ in range(3)] for _ in range(4)]
+
+        def z(t, deg=2):
+            t = mpmath.mpf(t)
+            return [sum(cf[j] * t ** j for j in range(deg + 1)) for cf in coef]
+
+        ts = [0.125, 0.25, 0.3125]
+        tn = 0.4375
+        tiny = mpmath.mpf(2) ** -380
+        # three points reproduce a quadratic, two a line, one a constant
+        assert max(abs(a - b) for a, b in zip(extrapolate(ts, [z(t) for t in ts], tn), z(tn))) < tiny
+        assert max(abs(a - b) for a, b in zip(extrapolate(ts[1:], [z(t, 1) for t in ts[1:]], tn), z(tn, 1))) < tiny
+        assert extrapolate(ts[2:], [z(ts[2])], tn) == z(ts[2])
+        # the secant through the last two points misses a quadratic by c (t' - t_1)(t' - t_2)
+        sec = extrapolate(ts[1:], [z(t) for t in ts[1:]], tn)
+        gap = (mpmath.mpf(tn) - ts[1]) * (mpmath.mpf(tn) - ts[2])
+        for v in range(4):
+            assert abs(z(tn)[v] - sec[v] - coef[v][2] * gap) < tiny
+        # the secant form used by the tracker: z + lam / (t - t_prev) (z - z_prev)
+        zp, zc = z(ts[1]), z(ts[2])
+        r = (mpmath.mpf(tn) - ts[2]) / (mpmath.mpf(ts[2]) - ts[1])
+        assert max(abs(a - (c + r * (c - b))) for a, b, c in zip(sec, zp, zc)) < tiny
+
+
+def test_quadratic_predictor_tracks_decoupled_closed_form_path():
+    d = [3, 4]
+    c_turns = [Fraction(1, 7), Fraction(2, 5)]
+    s = decoupled_system(d, c_turns, Fraction(3, 11))
+    k = [1, 2]
+    x0 = start_root(np.array(d), np.array(k), s.L)
+    r = track_reference(s, x0, TrackParams(predictor="quadratic"), record=True)
+    assert not r.fail and r.t == 1.0
+    g = complex(mpc_of(s.gamma))
+    for t, z in r.history[1:]:
+        for i in range(2):
+            c = cmath.exp(2j * math.pi * float(c_turns[i]))
+            assert abs(complex(z[i]) - branch(d[i], k[i], c, g, t)) < 1e-9
+    # every prediction is the interpolant through the last (up to) three accepted points
+    with mpmath.workprec(prec_bits(s.L)):
+        acc = [(0.0, vec_mpc(x0))] + r.history
+    for t, _, tn, z, zq in r.predictions:
+        j = max(i for i, (ta, _) in enumerate(acc) if ta == t)
+        pts = acc[max(0, j - 2): j + 1]
+        assert z == pts[-1][1]
+        with mpmath.workprec(300):
+            ref = extrapolate([a for a, _ in pts], [b for _, b in pts], tn)
+            assert max(abs(a - b) for a, b in zip(ref, zq)) < 1e-60
+    # the quadratic predictor leaves smaller first Newton corrections than the secant on this smooth path
+    sec = track_reference(s, x0, record=True)
+    assert r.newton_iterations <= sec.newton_iterations
 
 
 def test_stationary_path_when_target_is_start_system():
