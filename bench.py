@@ -118,6 +118,28 @@ def track_case(q, name, L):
             "fail": st["fail"]}
 
 
+def quality_report(dd, qd, cpu):
+    """Quality up of Section 2 on the n = 64 workload: the same path tracked in
+    double double and in quad double on the GPU.  Q = correct decimal places
+    against the exact root; the fixed-time reference is the oracle's double
+    double Newton step on one host core, times the Newton iterations of the
+    GPU double-double path (an extrapolation: the oracle does not track the
+    whole path)."""
+    rep = {
+        "workload": "n=64, 64 monomials per polynomial, exponents in {0..4}, seed 2; the same draws rounded to "
+                    "2 limbs (double double) and 4 limbs (quad double)",
+        "Q_dd": dd["correct_digits"], "T_dd_s": dd["seconds"],
+        "Q_qd": qd["correct_digits"], "T_qd_s": qd["seconds"],
+        "quality_up": qd["correct_digits"] / dd["correct_digits"],
+        "time_ratio_qd_over_dd": qd["seconds"] / dd["seconds"],
+    }
+    if cpu:
+        t1 = dd["newton_iterations"] / cpu["value"]
+        rep["oracle_dd_path_s_extrapolated"] = t1
+        rep["qd_gpu_faster_than_oracle_dd"] = qd["seconds"] < t1
+    return rep
+
+
 def measured_traffic(kernel_file: str):
     """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary of
     the dominant kernel, or None when the kernel's sources changed since the
@@ -250,9 +272,12 @@ def main():
             extra.append({"workload": name, "solve": "full" if md == 0 else "mixed", "steps_per_s": r,
                           "ms_per_step": m_, "eval_us": e_, "solve_us": g_, "refine_steps": inf["refine_steps"]})
         out["solve_modes"] = extra
+    paths = {}
     if not args.no_paths:
         try:
-            out["paths"] = [track_case(q, "n8_dd", 2), track_case(q, "n32_dd", 2)]
+            for name, lim in (("n8_dd", 2), ("n32_dd", 2), ("n64_dd", 2), ("n64_qd", 4)):
+                paths[name] = track_case(q, name, lim)
+            out["paths"] = list(paths.values())
         except Exception as e:  # report, never hide, a failing path
             out["paths"] = [{"error": str(e)}]
     if not args.no_cpu_baseline:
@@ -261,6 +286,8 @@ def main():
         with open(os.path.join(ROOT, "tests", "golden", "path_n64_dd.json")) as fh:
             fix = json.load(fh)
         out["cpu_baseline"] = cpu_baseline(config_system(cfg), path_point(fix, L), t)
+    if "n64_dd" in paths and "n64_qd" in paths:
+        out["quality_up"] = quality_report(paths["n64_dd"], paths["n64_qd"], out.get("cpu_baseline"))
     print(json.dumps(out))
 
 

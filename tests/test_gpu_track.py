@@ -45,6 +45,14 @@ def test_track_n32_dd_endpoint_digits():
     assert correct_digits(z, zss) >= 28
 
 
+def test_track_n64_dd_and_qd_endpoint_digits():
+    # the quality-up pair of the n = 64 workload: the same draws in double double and quad double
+    z, st, zss = track_config("n64_dd")
+    assert not st["fail"] and correct_digits(z, zss) >= 28
+    z, st, zss = track_config("n64_qd")
+    assert not st["fail"] and correct_digits(z, zss) >= 60
+
+
 def test_track_decoupled_closed_form():
     import paper_1109_0545_amd as q
 
