@@ -33,6 +33,11 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic flops per complex operation in double double, counted from the
 # textbook double-double formulas: complex multiply 80, add 40, fma 120
 CMUL, CADD, CFMA = 80, 40, 120
+# quad double: FP64 operations (FMA = 2) of this library's quad-double routines:
+# real add 70 (level-by-level sums, renormalisation), real multiply 129, so
+# complex multiply 4*129 + 2*70 = 656, add 140, fma 796
+QD_CMUL, QD_CADD, QD_CFMA = 656, 140, 796
+FLOPS = {2: (CMUL, CADD, CFMA), 4: (QD_CMUL, QD_CADD, QD_CFMA), 1: (6, 2, 8)}
 
 
 def ge_cfma(n: int) -> int:
@@ -158,9 +163,12 @@ def measured_traffic(kernel_file: str):
     return rec["bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
 
 
-def newton_rate(q, name: str, L: int, mode: int, steps: int, warmup: int, t: float = 0.5):
+def newton_rate(q, name: str, L: int, mode: int, steps: int, warmup: int, t: float = 0.5, B: int = 1):
     """Newton steps/s of one workload at fixed t with the convergence exit off;
-    returns (steps/s, ms/step, eval us/launch, solve us/launch, system)."""
+    returns (steps/s summed over the B points, ms per iteration, eval us/launch,
+    solve us/launch, system, info of point 0).  B > 1: B points of the path
+    (the stored point scaled by 1 + 1e-6 b) in one launch per kernel."""
+    import numpy as np
     import torch
 
     from synth.systems import CONFIGS, config_system
@@ -171,21 +179,42 @@ def newton_rate(q, name: str, L: int, mode: int, steps: int, warmup: int, t: flo
     S = q.System.from_synth(sysm)
     H = q.Homotopy(S, sysm.gamma)
     stream = torch.cuda.current_stream()
-    x = torch.from_numpy(path_point(fix, L)).cuda()
-    q.newton_step_dev(H, t, x, L, mode, eps=0.0, max_it=warmup, stream=stream)
-    torch.cuda.synchronize()
-    q.binding.set_timing(True)
+    p0 = path_point(fix, L)
+    x = torch.from_numpy(np.stack([p0 * (1.0 + 1e-6 * b) for b in range(B)])).cuda()
+    q.newton_batch_dev(H, t, x, B, L, mode, eps=0.0, max_it=warmup, stream=stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    q.newton_step_dev(H, t, x, L, mode, eps=0.0, max_it=steps, stream=stream)
+    q.newton_batch_dev(H, t, x, B, L, mode, eps=0.0, max_it=steps, stream=stream)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    infos = q.last_info_batch(H, L, B, stream=stream)
+    if any(i["iterations"] != steps for i in infos):
+        raise RuntimeError(f"{name}: not every point ran {steps} Newton iterations: {infos[:2]}")
+    # per-kernel durations from HIP events between the kernels, in a separate
+    # run (the events add gaps between launches, so the timed run has none)
+    q.binding.set_timing(True)
+    q.newton_batch_dev(H, t, x, B, L, mode, eps=0.0, max_it=min(steps, 500), stream=stream)
+    torch.cuda.synchronize()
     q.binding.set_timing(False)
-    info = q.last_info(H, L, stream=stream)
-    if info["iterations"] != steps:
-        raise RuntimeError(f"{name}: only {info['iterations']} of {steps} Newton iterations ran: {info}")
     eval_ms, solve_ms, launches = q.binding.last_timing(H, L, stream=stream)
-    return steps / el, el / steps * 1e3, eval_ms / launches * 1e3, solve_ms / launches * 1e3, sysm, info
+    return B * steps / el, el / steps * 1e3, eval_ms / launches * 1e3, solve_ms / launches * 1e3, sysm, infos[0]
+
+
+def eval_flops(sysm, L: int) -> int:
+    cm, ca = eval_ops(sysm.exps, sysm.poly_offsets)
+    fm, fa, _ = FLOPS[L]
+    return cm * fm + ca * fa
+
+
+def rate_entry(name, L, B, mode, rate, ms, ev_us, ge_us, sysm):
+    """Per-kernel algorithmic rates of one Newton timing run (B points per launch)."""
+    n = sysm.n
+    evf = B * eval_flops(sysm, L)
+    gef = B * (ge_cfma(n) + bs_cfma(n)) * FLOPS[L][2]
+    return {"workload": name, "B": B, "solve": "full" if mode == 0 else "mixed", "steps_per_s": rate,
+            "ms_per_iteration": ms, "eval_us": ev_us, "solve_us": ge_us,
+            "eval_tflops": evf / ev_us / 1e6, "eval_frac_fp64_peak": evf / ev_us / 1e6 / FP64_PEAK_TFLOPS,
+            "solve_tflops": gef / ge_us / 1e6 if mode == 0 else None}
 
 
 def main():
@@ -197,6 +226,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-paths", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the mixed-precision / n=128 comparison lines")
+    ap.add_argument("--batch", type=int, default=256, help="points per launch of the batched comparison line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 256 MiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -266,11 +296,16 @@ def main():
         "kernels": {"eval_us": ev_us, "solve_us": ge_us, "eval_flops": ev_flops, "solve_flops": ge_flops},
     }
     if not args.no_extra:
-        extra = []
-        for name, md, k in (("n64_dd", 1 - mode, max(args.steps // 2, 10)), ("n128_dd", 0, 200), ("n128_dd", 1, 200)):
-            r, m_, e_, g_, _, inf = newton_rate(q, name, L, md, k, 10, t)
-            extra.append({"workload": name, "solve": "full" if md == 0 else "mixed", "steps_per_s": r,
-                          "ms_per_step": m_, "eval_us": e_, "solve_us": g_, "refine_steps": inf["refine_steps"]})
+        extra = [rate_entry("n64_dd", L, 1, mode, rate, ms, ev_us, ge_us, sysm)]
+        for name, lim, md, k, B in (("n64_dd", 2, 1 - mode, max(args.steps // 2, 10), 1),
+                                    ("n128_dd", 2, 0, 200, 1), ("n128_dd", 2, 1, 200, 1),
+                                    ("n64_qd", 4, 0, 200, 1),
+                                    ("n64_dd", 2, 0, 100, args.batch)):
+            r, m_, e_, g_, sy, inf = newton_rate(q, name, lim, md, k, 10, t, B=B)
+            ent = rate_entry(name, lim, B, md, r, m_, e_, g_, sy)
+            ent["refine_steps"] = inf["refine_steps"]
+            extra.append(ent)
+        # B points per launch: independent paths at one t (the rate summed over points)
         out["solve_modes"] = extra
     paths = {}
     if not args.no_paths:

@@ -96,6 +96,16 @@ qdp_status qdp_eval_homotopy(const qdp_homotopy *h, double t, const double *x, q
                              double *jac, double *scale, void *hip_stream);
 qdp_status qdp_eval_homotopy_dev(const qdp_homotopy *h, double t, const double *x, qdp_prec prec, double *y,
                                  double *jac, double *scale, void *hip_stream);
+/* The same at B points in one launch (device memory, asynchronous): x [B][n][2][L],
+ * y [B][n][2][L], jac [B][n][n][2][L], scale [B][n] (nullable), point b's block
+ * following point b-1's.  The monomials of a polynomial may be split over several
+ * workgroups whose partial sums are added in a fixed order: results are
+ * reproducible for a given (system, B) but may differ in the last bits from
+ * qdp_eval_homotopy_dev, which uses one workgroup per polynomial.  Uses scratch
+ * memory of h (allocated on first use or growth of B, which synchronises the
+ * device): calls on one h must not overlap.  1 <= B <= 65536. */
+qdp_status qdp_eval_homotopy_batch_dev(const qdp_homotopy *h, double t, const double *x, int32_t B,
+                                       qdp_prec prec, double *y, double *jac, double *scale, void *hip_stream);
 
 typedef struct {
   int32_t iterations;   /* Newton iterations run */
@@ -126,15 +136,26 @@ qdp_status qdp_newton_step(const qdp_homotopy *h, double t, double *x, qdp_prec 
 /* Same with x in device memory; asynchronous; read info with qdp_homotopy_last_info. */
 qdp_status qdp_newton_step_dev(const qdp_homotopy *h, double t, double *x, qdp_prec prec, qdp_solve mode,
                                double eps, int32_t max_it, void *hip_stream);
-/* Synchronise hip_stream and return the info of the last Newton call on h at precision prec. */
+/* Synchronise hip_stream and return the info of the last Newton call on h at precision prec
+ * (of its first point for a batch call). */
 qdp_status qdp_homotopy_last_info(const qdp_homotopy *h, qdp_prec prec, qdp_newton_info *info, void *hip_stream);
+/* Algorithm 4.1 at B independent points of the same homotopy and t (B paths at
+ * one value of the parameter), x [B][n][2][L] in device memory, updated in place;
+ * each point runs its own loop (own residual test and iteration count).  One
+ * launch per kernel covers all points; asynchronous.  Calls on one h must not
+ * overlap.  1 <= B <= 65536. */
+qdp_status qdp_newton_batch_dev(const qdp_homotopy *h, double t, double *x, int32_t B, qdp_prec prec,
+                                qdp_solve mode, double eps, int32_t max_it, void *hip_stream);
+/* Synchronise and return info[0..B-1] of the last Newton call on h at precision prec. */
+qdp_status qdp_homotopy_last_info_batch(const qdp_homotopy *h, qdp_prec prec, int32_t B, qdp_newton_info *info,
+                                        void *hip_stream);
 
 /* ---- learned step control (a growth direction of the tracker, not in the paper) ----
  * A step-size network: widths w_0 (features) .. w_last (outputs), ReLU hidden
  * layers; parameters are FP32, flat: for each layer its weights [out][in]
  * (row-major) then its bias [out].  Outputs 0 .. w_last-2 are logits of
  * "a step of lambda * 2^(k-1) would be accepted" (k = 0..w_last-2); the last
- * output is the weight of the secant term in the predictor.  Training loss,
+ * output is the weight of the quadratic predictor against the secant.  Training loss,
  * over a batch of B rows with targets Y and a 0/1 mask M (both [B][w_last]):
  *   (1/B) sum_b [ sum_{k<last} M_bk BCE(o_bk, Y_bk) + M_b,last (o_b,last - Y_b,last)^2 ]. */
 typedef struct qdp_policy qdp_policy;

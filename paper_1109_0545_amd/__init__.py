@@ -25,7 +25,10 @@ from .binding import (  # noqa: F401
     eval_homotopy_dev,
     eval_jacobian,
     eval_jacobian_dev,
+    eval_homotopy_batch_dev,
     last_info,
+    last_info_batch,
+    newton_batch_dev,
     lib,
     newton_step,
     newton_step_dev,

@@ -138,6 +138,10 @@ SIGNATURES = {
                                    ct.POINTER(NewtonInfo), _P]),
     "qdp_newton_step_dev": (ct.c_int, [_P, ct.c_double, _P, ct.c_int, ct.c_int, ct.c_double, ct.c_int32, _P]),
     "qdp_homotopy_last_info": (ct.c_int, [_P, ct.c_int, ct.POINTER(NewtonInfo), _P]),
+    "qdp_eval_homotopy_batch_dev": (ct.c_int, [_P, ct.c_double, _P, ct.c_int32, ct.c_int, _P, _P, _P, _P]),
+    "qdp_newton_batch_dev": (ct.c_int, [_P, ct.c_double, _P, ct.c_int32, ct.c_int, ct.c_int, ct.c_double,
+                                        ct.c_int32, _P]),
+    "qdp_homotopy_last_info_batch": (ct.c_int, [_P, ct.c_int, ct.c_int32, ct.POINTER(NewtonInfo), _P]),
     "qdp_track_params_default": (ct.c_int, [ct.POINTER(TrackParams)]),
     "qdp_track_path": (ct.c_int, [_P, _P, ct.c_int, ct.POINTER(TrackParams), ct.POINTER(TrackStats),
                                   ct.POINTER(StepRecord), ct.c_int64, _P]),
@@ -346,6 +350,24 @@ def eval_homotopy(h: Homotopy, t: float, x: np.ndarray, prec: int, stream=None):
 def eval_homotopy_dev(h: Homotopy, t: float, x, prec: int, y, jac, scale=None, stream=None) -> None:
     _check(lib().qdp_eval_homotopy_dev(h.handle, float(t), _ptr(x), prec, _ptr(y), _ptr(jac), _ptr(scale),
                                        _stream(stream)))
+
+
+def eval_homotopy_batch_dev(h: Homotopy, t: float, x, B: int, prec: int, y, jac, scale=None, stream=None) -> None:
+    """B points x [B][n][2][prec] (device) -> y [B][n][2][prec], jac [B][n][n][2][prec], scale [B][n]."""
+    _check(lib().qdp_eval_homotopy_batch_dev(h.handle, float(t), _ptr(x), int(B), prec, _ptr(y), _ptr(jac),
+                                             _ptr(scale), _stream(stream)))
+
+
+def newton_batch_dev(h: Homotopy, t: float, x, B: int, prec: int, mode: int = SOLVE_FULL, eps: float = 1e-10,
+                     max_it: int = 4, stream=None) -> None:
+    _check(lib().qdp_newton_batch_dev(h.handle, float(t), _ptr(x), int(B), prec, mode, float(eps), int(max_it),
+                                      _stream(stream)))
+
+
+def last_info_batch(h: Homotopy, prec: int, B: int, stream=None) -> list:
+    infos = (NewtonInfo * B)()
+    _check(lib().qdp_homotopy_last_info_batch(h.handle, prec, int(B), infos, _stream(stream)))
+    return [infos[b].as_dict() for b in range(B)]
 
 
 def newton_step(h: Homotopy, t: float, x: np.ndarray, prec: int, mode: int = SOLVE_FULL, eps: float = 1e-10,

@@ -17,17 +17,17 @@
 #include "common.hpp"
 
 namespace qdp {
-hipError_t launch_ge_scaled(int L, int n, double *ab, double *scale, double *x, double *dz, NewtonState *st,
+hipError_t launch_ge_scaled(int L, int n, int B, double *ab, double *scale, double *x, double *dz, NewtonState *st,
                             hipStream_t s);
 hipError_t launch_arith(int op, int L, int64_t count, const double *a, const double *b, const double *c,
                         double *out, hipStream_t s);
-hipError_t launch_init_state(NewtonState *st, double eps, int max_it, hipStream_t s);
+hipError_t launch_init_state(NewtonState *st, int B, double eps, int max_it, hipStream_t s);
 hipError_t launch_predict(int L, int n, const double *x, const double *xprev, const double *xprev2, double c1,
                           double c2, double *xpred, double *aux, hipStream_t s);
 hipError_t launch_blend_label(int L, int n, const double *x, const double *xprev, const double *xprev2,
                               const double *xcorr, double s1, double q1, double q2, double *aux, hipStream_t s);
 hipError_t launch_copy(double *dst, const double *src, size_t count, hipStream_t s);
-hipError_t launch_mixed_solve(int n, double *ab, double *scale, double *x, NewtonState *st, double *lu,
+hipError_t launch_mixed_solve(int n, int B, double *ab, double *scale, double *x, NewtonState *st, double *lu,
                               double *work, int refinements, hipStream_t s);
 }  // namespace qdp
 
@@ -75,17 +75,19 @@ struct qdp_system {
 
 struct Workspace {
   int L = 0;
-  double *ab = nullptr;     // (n+1) x n column-major [A | -h]
-  double *scale = nullptr;  // [n]
+  int bcap = 0;             // points the batch-sized buffers hold
+  double *ab = nullptr;     // [bcap] (n+1) x n column-major [A | -h]
+  double *scale = nullptr;  // [bcap][n]
+  double *part = nullptr;   // split-evaluation partial rows (EvalSplit)
   double *x = nullptr;      // [n] point (compute precision)
   double *xprev = nullptr;  // [n] previous accepted point
   double *xprev2 = nullptr; // [n] the accepted point before that
   double *xw = nullptr;     // [n] working point (predicted / corrected)
   double *y = nullptr;      // [n] values (eval entry points)
   double *jac = nullptr;    // [n][n] Jacobian (eval entry points)
-  double *lu = nullptr;     // mixed precision: FP64 factors
+  double *lu = nullptr;     // [bcap] mixed precision: FP64 factors
   double *work = nullptr;   // mixed precision scratch
-  NewtonState *st = nullptr;
+  NewtonState *st = nullptr;  // [bcap]
   double *aux = nullptr;       // [4] predictor distance, blend-label sums
   std::vector<hipEvent_t> ev;  // timing: 3 events per iteration (before eval, between, after solve)
   int timed_its = 0;
@@ -100,43 +102,61 @@ struct qdp_homotopy {
 
 static int ws_index(int L) { return L == 1 ? 0 : (L == 2 ? 1 : 2); }
 
-static qdp_status ensure_ws(qdp_homotopy *h, int L, Workspace **out) {
+static void free_batch(Workspace &w) {
+  hipFree(w.ab);
+  hipFree(w.scale);
+  hipFree(w.part);
+  hipFree(w.lu);
+  hipFree(w.st);
+  w.ab = w.scale = w.part = w.lu = nullptr;
+  w.st = nullptr;
+  w.bcap = 0;
+}
+
+// Workspace of (h, L) able to hold B points; growing it waits for the device
+// (earlier asynchronous work may still use the old buffers).
+static qdp_status ensure_ws(qdp_homotopy *h, int L, int B, Workspace **out) {
   Workspace &w = h->ws[ws_index(L)];
   const int n = h->f->n;
-  if (!w.ab) {
-    const size_t e = 2 * (size_t)L;
-    HIPCHK(hipMalloc(&w.ab, (size_t)n * (n + 1) * e * sizeof(double)));
-    HIPCHK(hipMalloc(&w.scale, (size_t)n * sizeof(double)));
+  const size_t e = 2 * (size_t)L;
+  if (!w.x) {
     HIPCHK(hipMalloc(&w.x, (size_t)n * e * sizeof(double)));
     HIPCHK(hipMalloc(&w.xprev, (size_t)n * e * sizeof(double)));
     HIPCHK(hipMalloc(&w.xprev2, (size_t)n * e * sizeof(double)));
     HIPCHK(hipMalloc(&w.xw, (size_t)n * e * sizeof(double)));
     HIPCHK(hipMalloc(&w.y, (size_t)n * e * sizeof(double)));
     HIPCHK(hipMalloc(&w.jac, (size_t)n * n * e * sizeof(double)));
-    HIPCHK(hipMalloc(&w.st, sizeof(NewtonState)));
     HIPCHK(hipMalloc(&w.aux, 4 * sizeof(double)));
-    if (L == 2) {
-      HIPCHK(hipMalloc(&w.lu, (size_t)n * (n + 1) * 2 * sizeof(double)));
-      HIPCHK(hipMalloc(&w.work, (size_t)n * 8 * 2 * sizeof(double)));
-    }
+    if (L == 2) HIPCHK(hipMalloc(&w.work, (size_t)n * 8 * 2 * sizeof(double)));
     w.L = L;
+  }
+  if (B > w.bcap) {
+    if (w.bcap > 0) {
+      HIPCHK(hipDeviceSynchronize());
+      free_batch(w);
+    }
+    const size_t Bs = (size_t)B;
+    HIPCHK(hipMalloc(&w.ab, Bs * n * (n + 1) * e * sizeof(double)));
+    HIPCHK(hipMalloc(&w.scale, Bs * n * sizeof(double)));
+    HIPCHK(hipMalloc(&w.st, Bs * sizeof(NewtonState)));
+    const size_t pd = qdp::eval_part_doubles(L, n, B);
+    if (pd > 0) HIPCHK(hipMalloc(&w.part, pd * sizeof(double)));
+    if (L == 2) HIPCHK(hipMalloc(&w.lu, Bs * n * (n + 1) * 2 * sizeof(double)));
+    w.bcap = B;
   }
   *out = &w;
   return QDP_OK;
 }
 
 static void free_ws(Workspace &w) {
-  hipFree(w.ab);
-  hipFree(w.scale);
+  free_batch(w);
   hipFree(w.x);
   hipFree(w.xprev);
   hipFree(w.xprev2);
   hipFree(w.xw);
   hipFree(w.y);
   hipFree(w.jac);
-  hipFree(w.lu);
   hipFree(w.work);
-  hipFree(w.st);
   hipFree(w.aux);
   for (auto &e : w.ev) hipEventDestroy(e);
   w = Workspace();
@@ -269,8 +289,9 @@ static qdp_status eval_common(const qdp_system *f, const qdp_homotopy *h, double
   if (!x_dev || !y_dev || !jac_dev) return fail(QDP_EINVAL, "NULL buffer");
   // row-major [i][v][2][L] and [i][2][L]: limb c at offset c
   const long e = 2 * L;
-  qdp::EvalOut o{jac_dev, 1, (long)f->n * e, e, y_dev, 1, e, 1.0, scale_dev};
-  HIPCHK(qdp::launch_eval(L, f->dev(), x_dev, hom_args(h, L, t, h != nullptr), o, nullptr, st));
+  qdp::EvalOut o{jac_dev, 1, (long)f->n * e, e, y_dev, 1, e, 1.0, scale_dev, 0, 0, 0};
+  const qdp::EvalSplit whole{nullptr, 1};  // one workgroup per polynomial: no scratch
+  HIPCHK(qdp::launch_eval(L, f->dev(), x_dev, 0, 1, hom_args(h, L, t, h != nullptr), o, nullptr, whole, st));
   return QDP_OK;
 }
 
@@ -340,14 +361,17 @@ extern "C" qdp_status qdp_eval_homotopy(const qdp_homotopy *h, double t, const d
 // update).  Every kernel reads the device flag `active` first and returns at
 // once when the loop of Algorithm 4.1 has ended, so the host never waits
 // between iterations.
-static qdp_status enqueue_newton(qdp_homotopy *h, Workspace *w, int L, double t, double *x_dev, int mode,
+static qdp_status enqueue_newton(qdp_homotopy *h, Workspace *w, int L, double t, double *x_dev, int B, int mode,
                                  double eps, int max_it, hipStream_t st) {
   const qdp_system *f = h->f;
   const int n = f->n;
-  HIPCHK(qdp::launch_init_state(w->st, eps, max_it, st));
-  // [A | -h] column-major in limb planes: limb c of (r,k) at c*n(n+1) + k*n + r
+  HIPCHK(qdp::launch_init_state(w->st, B, eps, max_it, st));
+  // [A | -h] column-major in limb planes: limb c of (r,k) at c*n(n+1) + k*n + r,
+  // one such block per point
   const long ps = (long)n * (n + 1);
-  qdp::EvalOut o{w->ab, ps, 1, n, w->ab + (size_t)n * n, ps, 1, -1.0, w->scale};
+  const long pb = ps * 2 * L;
+  qdp::EvalOut o{w->ab, ps, 1, n, w->ab + (size_t)n * n, ps, 1, -1.0, w->scale, pb, pb, n};
+  const qdp::EvalSplit split{w->part, qdp::kMaxEvalParts};
   const qdp::HomArgs ha = hom_args(h, L, t, 1);
   const bool timing = g_timing != 0;
   if (timing) {
@@ -360,12 +384,12 @@ static qdp_status enqueue_newton(qdp_homotopy *h, Workspace *w, int L, double t,
   w->timed_its = timing ? max_it : 0;
   for (int it = 0; it < max_it; ++it) {
     if (timing) HIPCHK(hipEventRecord(w->ev[3 * it], st));
-    HIPCHK(qdp::launch_eval(L, f->dev(), x_dev, ha, o, w->st, st));
+    HIPCHK(qdp::launch_eval(L, f->dev(), x_dev, (long)n * 2 * L, B, ha, o, w->st, split, st));
     if (timing) HIPCHK(hipEventRecord(w->ev[3 * it + 1], st));
     if (mode == QDP_SOLVE_MIXED_IR)
-      HIPCHK(qdp::launch_mixed_solve(n, w->ab, w->scale, x_dev, w->st, w->lu, w->work, 3, st));
+      HIPCHK(qdp::launch_mixed_solve(n, B, w->ab, w->scale, x_dev, w->st, w->lu, w->work, 3, st));
     else
-      HIPCHK(qdp::launch_ge_scaled(L, n, w->ab, w->scale, x_dev, nullptr, w->st, st));
+      HIPCHK(qdp::launch_ge_scaled(L, n, B, w->ab, w->scale, x_dev, nullptr, w->st, st));
     if (timing) HIPCHK(hipEventRecord(w->ev[3 * it + 2], st));
   }
   return QDP_OK;
@@ -404,12 +428,47 @@ extern "C" qdp_status qdp_newton_step_dev(const qdp_homotopy *hc, double t, doub
   auto *h = const_cast<qdp_homotopy *>(hc);
   std::lock_guard<std::mutex> g(h->mu);
   Workspace *w = nullptr;
-  if ((s = ensure_ws(h, (int)prec, &w)) != QDP_OK) return s;
-  return enqueue_newton(h, w, (int)prec, t, x, mode, eps, max_it, (hipStream_t)stream);
+  if ((s = ensure_ws(h, (int)prec, 1, &w)) != QDP_OK) return s;
+  return enqueue_newton(h, w, (int)prec, t, x, 1, mode, eps, max_it, (hipStream_t)stream);
 }
 
-extern "C" qdp_status qdp_homotopy_last_info(const qdp_homotopy *hc, qdp_prec prec, qdp_newton_info *info,
-                                             void *stream) {
+extern "C" qdp_status qdp_newton_batch_dev(const qdp_homotopy *hc, double t, double *x, int32_t B, qdp_prec prec,
+                                           qdp_solve mode, double eps, int32_t max_it, void *stream) {
+  qdp_status s = newton_checks(hc, t, x, (int)prec, mode, eps, max_it);
+  if (s != QDP_OK) return s;
+  if (B < 1 || B > (1 << 16)) return fail(QDP_EINVAL, "B must be in [1, 65536]");
+  auto *h = const_cast<qdp_homotopy *>(hc);
+  std::lock_guard<std::mutex> g(h->mu);
+  Workspace *w = nullptr;
+  if ((s = ensure_ws(h, (int)prec, B, &w)) != QDP_OK) return s;
+  return enqueue_newton(h, w, (int)prec, t, x, B, mode, eps, max_it, (hipStream_t)stream);
+}
+
+extern "C" qdp_status qdp_eval_homotopy_batch_dev(const qdp_homotopy *hc, double t, const double *x, int32_t B,
+                                                  qdp_prec prec, double *y, double *jac, double *scale,
+                                                  void *stream) {
+  if (!hc) return fail(QDP_EINVAL, "NULL homotopy");
+  if (!std::isfinite(t)) return fail(QDP_ENONFINITE, "non-finite t");
+  const int L = (int)prec;
+  if (!valid_prec(L) || L > hc->f->L) return fail(QDP_EINVAL, "prec must be 1, 2 or 4 and not above the system's");
+  if (!x || !y || !jac) return fail(QDP_EINVAL, "NULL buffer");
+  if (B < 1 || B > (1 << 16)) return fail(QDP_EINVAL, "B must be in [1, 65536]");
+  auto *h = const_cast<qdp_homotopy *>(hc);
+  std::lock_guard<std::mutex> g(h->mu);
+  Workspace *w = nullptr;
+  qdp_status s = ensure_ws(h, L, B, &w);
+  if (s != QDP_OK) return s;
+  const int n = h->f->n;
+  const long e = 2 * L;
+  qdp::EvalOut o{jac, 1, (long)n * e, e, y, 1, e, 1.0, scale, (long)n * n * e, (long)n * e, n};
+  const qdp::EvalSplit split{w->part, qdp::kMaxEvalParts};
+  HIPCHK(qdp::launch_eval(L, h->f->dev(), x, (long)n * e, B, hom_args(h, L, t, 1), o, nullptr, split,
+                          (hipStream_t)stream));
+  return QDP_OK;
+}
+
+extern "C" qdp_status qdp_homotopy_last_info_batch(const qdp_homotopy *hc, qdp_prec prec, int32_t B,
+                                                   qdp_newton_info *info, void *stream) {
   if (!hc || !info) return fail(QDP_EINVAL, "NULL argument");
   if (!valid_prec((int)prec)) return fail(QDP_EINVAL, "prec must be 1, 2 or 4");
   auto *h = const_cast<qdp_homotopy *>(hc);
@@ -417,10 +476,16 @@ extern "C" qdp_status qdp_homotopy_last_info(const qdp_homotopy *hc, qdp_prec pr
   HIPCHK(hipStreamSynchronize((hipStream_t)stream));
   Workspace &w = h->ws[ws_index((int)prec)];
   if (!w.st) return fail(QDP_EINVAL, "no Newton call on this homotopy at this precision yet");
-  NewtonState ns;
-  HIPCHK(hipMemcpy(&ns, w.st, sizeof(ns), hipMemcpyDeviceToHost));
-  info_from_state(ns, info);
+  if (B < 1 || B > w.bcap) return fail(QDP_EINVAL, "B must be in [1, points of the workspace]");
+  std::vector<NewtonState> ns(B);
+  HIPCHK(hipMemcpy(ns.data(), w.st, B * sizeof(NewtonState), hipMemcpyDeviceToHost));
+  for (int b = 0; b < B; ++b) info_from_state(ns[b], info + b);
   return QDP_OK;
+}
+
+extern "C" qdp_status qdp_homotopy_last_info(const qdp_homotopy *hc, qdp_prec prec, qdp_newton_info *info,
+                                             void *stream) {
+  return qdp_homotopy_last_info_batch(hc, prec, 1, info, stream);
 }
 
 extern "C" qdp_status qdp_newton_step(const qdp_homotopy *hc, double t, double *x, qdp_prec prec,
@@ -433,11 +498,11 @@ extern "C" qdp_status qdp_newton_step(const qdp_homotopy *hc, double t, double *
   if ((s = check_point(h->f->n, L, x)) != QDP_OK) return s;
   std::lock_guard<std::mutex> g(h->mu);
   Workspace *w = nullptr;
-  if ((s = ensure_ws(h, L, &w)) != QDP_OK) return s;
+  if ((s = ensure_ws(h, L, 1, &w)) != QDP_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   const size_t bytes = (size_t)h->f->n * 2 * L * sizeof(double);
   HIPCHK(hipMemcpyAsync(w->xw, x, bytes, hipMemcpyHostToDevice, st));
-  if ((s = enqueue_newton(h, w, L, t, w->xw, mode, eps, max_it, st)) != QDP_OK) return s;
+  if ((s = enqueue_newton(h, w, L, t, w->xw, 1, mode, eps, max_it, st)) != QDP_OK) return s;
   NewtonState ns;
   HIPCHK(hipMemcpyAsync(x, w->xw, bytes, hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(&ns, w->st, sizeof(ns), hipMemcpyDeviceToHost, st));
@@ -581,7 +646,7 @@ extern "C" qdp_status qdp_track_path(const qdp_homotopy *hc, double *x, qdp_prec
   if (s != QDP_OK) return s;
   std::lock_guard<std::mutex> g(h->mu);
   Workspace *w = nullptr;
-  if ((s = ensure_ws(h, L, &w)) != QDP_OK) return s;
+  if ((s = ensure_ws(h, L, 1, &w)) != QDP_OK) return s;
   hipStream_t st = (hipStream_t)stream;
   const size_t bytes = (size_t)n * 2 * L * sizeof(double);
   const auto t_start = std::chrono::steady_clock::now();
@@ -623,7 +688,7 @@ extern "C" qdp_status qdp_track_path(const qdp_homotopy *hc, double *x, qdp_prec
       c2 = wq * q2;
     }
     HIPCHK(qdp::launch_predict(L, n, w->x, w->xprev, w->xprev2, c1, c2, w->xw, w->aux, st));
-    qdp_status e = enqueue_newton(h, w, L, tn, w->xw, p.mode, p.eps_path, p.max_it_path, st);
+    qdp_status e = enqueue_newton(h, w, L, tn, w->xw, 1, p.mode, p.eps_path, p.max_it_path, st);
     if (e != QDP_OK) return e;
     HIPCHK(hipMemcpyAsync(&ns, w->st, sizeof(ns), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(aux, w->aux, sizeof(aux), hipMemcpyDeviceToHost, st));
@@ -762,7 +827,7 @@ extern "C" qdp_status qdp_track_path(const qdp_homotopy *hc, double *x, qdp_prec
     double rho = 1.0;
     int it = 0;
     while (rho > eps_end && it < p.max_it_end) {
-      if ((s = enqueue_newton(h, w, L, 1.0, w->x, p.mode, 0.0, 1, st)) != QDP_OK) return s;
+      if ((s = enqueue_newton(h, w, L, 1.0, w->x, 1, p.mode, 0.0, 1, st)) != QDP_OK) return s;
       HIPCHK(hipMemcpyAsync(&ns, w->st, sizeof(ns), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       rho = ns.rho;

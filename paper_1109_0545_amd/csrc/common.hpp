@@ -25,9 +25,9 @@ struct DevSystem {
 };
 
 // Where evaluation results go.  All strides count doubles.  Limb c of the
-// complex element J(i,v) (c < L real limbs, then L imaginary limbs) sits at
-// J[c*psJ + i*rsJ + v*csJ]; limb c of value i at y[c*psy + i*sy] (times
-// ysign); scale_i -> scale[i] (nullable).
+// complex element J(i,v) of point b (c < L real limbs, then L imaginary
+// limbs) sits at J[b*bJ + c*psJ + i*rsJ + v*csJ]; limb c of value i at
+// y[b*by + c*psy + i*sy] (times ysign); scale_i -> scale[b*bS + i] (nullable).
 struct EvalOut {
   double *J;
   long psJ, rsJ, csJ;
@@ -35,7 +35,19 @@ struct EvalOut {
   long psy, sy;
   double ysign;
   double *scale;
+  long bJ, by, bS;
 };
+
+// Monomial split of the evaluation: with part != nullptr the monomials of a
+// polynomial may be spread over up to max_parts workgroups, whose partial
+// rows ([B][n][parts] records of (n+1) complex values and one scale sum) a
+// second kernel adds in part order.  part == nullptr: one workgroup per
+// polynomial.
+struct EvalSplit {
+  double *part;
+  int max_parts;
+};
+constexpr int kMaxEvalParts = 8;
 
 // Homotopy h = t f + (1-t) gamma (x^d - 1); homotopy = 0 evaluates f alone.
 struct HomArgs {
@@ -64,14 +76,12 @@ struct NewtonState {
   double xnorm;      // ||x||_inf after the last update
 };
 
-// launchers (defined per translation unit; return hipError_t)
-hipError_t launch_eval(int L, const DevSystem &s, const double *x, const HomArgs &h, const EvalOut &o,
-                       const NewtonState *gate, hipStream_t st);
-size_t eval_lds_bytes(int L, const DevSystem &s);
-
-hipError_t launch_ge(int L, int n, double *ab, double *x, double *dz, NewtonState *state, int update,
-                     hipStream_t st);
-hipError_t launch_mixed(int n, double *ab_dd, double *x, double *work, NewtonState *state, int max_refine,
-                        hipStream_t st);
+// Launchers (defined per translation unit; return hipError_t).  A launch
+// covers B independent points: x holds B points bx doubles apart, gate B
+// Newton states (nullable).
+hipError_t launch_eval(int L, const DevSystem &s, const double *x, long bx, int B, const HomArgs &h,
+                       const EvalOut &o, const NewtonState *gate, const EvalSplit &split, hipStream_t st);
+// Doubles of partial-row scratch a split evaluation of B points needs.
+size_t eval_part_doubles(int L, int n, int B);
 
 }  // namespace qdp

@@ -12,7 +12,10 @@
 // Section 6 folded into the table), so each variable of a monomial costs four
 // complex products, as the paper's scheme.
 //
-// Mapping on CDNA4: one workgroup per polynomial; a monomial is spread over
+// Mapping on CDNA4: one workgroup per polynomial, or, when that leaves the
+// chip idle, the monomials of a polynomial split over up to eight
+// workgroups that store partial rows, added in part order by a second small
+// kernel (see EvalSplit); blockIdx.y selects the point of a batch.  A monomial is spread over
 // LM lanes of a wavefront and lane g owns the CH variables g, g+LM, g+2LM, ...
 // (interleaved, so that neighbouring lanes read neighbouring table entries).
 // The order used for the prefix/suffix products is lane-major: a lane first
@@ -32,22 +35,133 @@ using namespace mw;
 
 template <int L> struct EvalArgs {
   DevSystem s;
-  const double *x;  // [n][2][L] at the compute precision
+  const double *x;  // [B][n][2][L] at the compute precision, points bx doubles apart
+  long bx;
   HomArgs h;
   EvalOut o;
-  const NewtonState *gate;
+  const NewtonState *gate;  // [B] or nullptr
+  int P;                    // workgroups per polynomial
+  double *part;             // P > 1: partial rows [B][n][P] records (part_record)
 };
+
+// doubles of one partial-row record: n+1 complex values, then the scale sum
+__host__ __device__ inline size_t part_record(int n, int L) { return (size_t)(n + 1) * 2 * L + 1; }
+__host__ __device__ inline size_t part_scale_at(int n, int L) { return (size_t)(n + 1) * 2 * L; }
+
+// Start-system powers of row i: pd1 = x_i^(d-1), pd = x_i^d by binary
+// powering in working precision (relative error about d units of the last
+// place); d = 0 gives pd1 = 0, pd = 1.
+template <int L> __device__ void start_powers(const double *xi_p, int d, C<L> &pd1, C<L> &pd) {
+  const C<L> xi = cload<L>(xi_p);
+  if (d >= 1) {
+    pd1 = cpow<L>(xi, d - 1);
+    pd = cmul<L>(pd1, xi);
+  } else {
+    pd1 = czero<L>();
+    pd = cone<L>();
+  }
+}
+
+// Homotopy blend and store of column col of row i of point b: s is the sum
+// over the monomials of f_i (col < n: the partial with respect to x_col;
+// col = n: the value, S its componentwise scale sum); pd1, pd the start-system
+// powers of row i (start_powers).
+template <int L>
+__device__ void eval_finish(const EvalArgs<L> &a, int b, int i, int col, C<L> s, double S, const C<L> &pd1,
+                            const C<L> &pd) {
+  const int n = a.s.n;
+  if (col < n) {
+    C<L> Jv = s;
+    if (a.h.homotopy) {
+      Jv = cmul_d<L>(s, a.h.t);
+      if (col == i) {
+        const C<L> g = cload<L>(a.h.gamma);
+        double e1;
+        R<L> omt = rzero<L>();
+        omt.v[0] = two_sum(1.0, -a.h.t, e1);
+        if (L > 1) omt.v[1] = e1;
+        const C<L> w = cmul_r<L>(g, omt);
+        const int d = a.s.deg[i];
+        if (d >= 1) Jv = cadd<L>(Jv, cmul<L>(w, cmul_d<L>(pd1, (double)d)));
+      }
+    }
+    pstore<L>(a.o.J + (size_t)b * a.o.bJ + (size_t)i * a.o.rsJ + (size_t)col * a.o.csJ, a.o.psJ, Jv);
+  } else {
+    C<L> hv = s;
+    if (a.h.homotopy) {
+      const C<L> g = cload<L>(a.h.gamma);
+      double e1;
+      R<L> omt = rzero<L>();
+      omt.v[0] = two_sum(1.0, -a.h.t, e1);
+      if (L > 1) omt.v[1] = e1;
+      const C<L> w = cmul_r<L>(g, omt);
+      C<L> gm = pd;
+      gm.re = rsub<L>(gm.re, rfrom<L>(1.0));
+      hv = cadd<L>(cmul_d<L>(s, a.h.t), cmul<L>(w, gm));
+      S = fabs(a.h.t) * S + cabs_hi<L>(w) * (cabs_hi<L>(pd) + 1.0);
+    }
+    if (a.o.ysign < 0) hv = cneg<L>(hv);
+    pstore<L>(a.o.y + (size_t)b * a.o.by + (size_t)i * a.o.sy, a.o.psy, hv);
+    if (a.o.scale) a.o.scale[(size_t)b * a.o.bS + i] = S;
+  }
+}
+
+// Second stage of a split evaluation: row i of point b is the sum of its P
+// partial rows in part order, then blended and stored.  Thread 0 forms the
+// start-system powers first (a short chain on an otherwise idle unit).
+template <int L>
+__global__ __launch_bounds__(256) void k_eval_sum(EvalArgs<L> a) {
+  const int b = blockIdx.y, i = blockIdx.x;
+  if (a.gate && !a.gate[b].active) return;
+  const int n = a.s.n;
+  const size_t rec = part_record(n, L);
+  const double *rows = a.part + ((size_t)b * n + i) * a.P * rec;
+  __shared__ double powbuf[4 * L];
+  if (threadIdx.x == 0 && a.h.homotopy) {
+    C<L> q1, q;
+    start_powers<L>(a.x + (size_t)b * a.bx + (size_t)i * 2 * L, a.s.deg[i], q1, q);
+    cstore<L>(powbuf, q1);
+    cstore<L>(powbuf + 2 * L, q);
+  }
+  __syncthreads();
+  C<L> pd1 = czero<L>(), pd = cone<L>();
+  if (a.h.homotopy) {
+    pd1 = cload<L>(powbuf);
+    pd = cload<L>(powbuf + 2 * L);
+  }
+  for (int col = threadIdx.x; col <= n; col += 256) {
+    // every load first (the parts are independent), then the fixed-order sum
+    C<L> v[kMaxEvalParts];
+#pragma unroll
+    for (int p = 0; p < kMaxEvalParts; ++p)
+      v[p] = p < a.P ? cload<L>(rows + (size_t)p * rec + (size_t)col * 2 * L) : czero<L>();
+    C<L> s = v[0];
+#pragma unroll
+    for (int p = 1; p < kMaxEvalParts; ++p)
+      if (p < a.P) s = cadd<L>(s, v[p]);
+    double S = 0.0;
+    if (col == n)
+      for (int p = 0; p < a.P; ++p) S += rows[(size_t)p * rec + part_scale_at(n, L)];
+    eval_finish<L>(a, b, i, col, s, S, pd1, pd);
+  }
+}
 
 // row stride (doubles) of a table plane: a multiple of 32 so that lanes with
 // consecutive variables read consecutive banks whatever their exponents
 __host__ __device__ inline int table_stride(int n) { return (n + 31) & ~31; }
 
+// NT threads work on monomials; with one part per polynomial (P = 1) the
+// launch adds a wavefront that forms the start-system powers meanwhile (a
+// chain of dependent products that would otherwise sit in the tail of the
+// workgroup); split evaluations form them in k_eval_sum.
 template <int L, int CH, int LM, int NT>
-__global__ __launch_bounds__(NT) void k_eval(EvalArgs<L> a) {
+__global__ __launch_bounds__(NT + 64) void k_eval(EvalArgs<L> a) {
   constexpr int G = 64 / LM;  // monomials per wavefront at a time
-  constexpr int W = NT / 64;  // wavefronts
+  constexpr int W = NT / 64;  // wavefronts on monomials
   constexpr int SLOTS = W * G;
-  if (a.gate && !a.gate->active) return;
+  const int b = blockIdx.y;
+  if (a.gate && !a.gate[b].active) return;
+  const double *x = a.x + (size_t)b * a.bx;
 
   extern __shared__ double smem[];
   const int n = a.s.n;
@@ -57,10 +171,12 @@ __global__ __launch_bounds__(NT) void k_eval(EvalArgs<L> a) {
   double *Gt = smem;                   // x_v^e          plane c at Gt + c*tps + e*nv + v
   double *Qt = smem + 2 * L * tps;     // e x_v^(e-1)
   const int tid = threadIdx.x;
+  const bool pw = tid >= NT;  // the start-power wavefront
+  __shared__ double powbuf[4 * L];
 
   // ---- power tables
-  for (int v = tid; v < n; v += NT) {
-    const C<L> xv = cload<L>(a.x + (size_t)v * 2 * L);
+  for (int v = tid; v < n && !pw; v += NT) {
+    const C<L> xv = cload<L>(x + (size_t)v * 2 * L);
     C<L> p = cone<L>();
     pstore<L>(Gt + v, tps, p);
     pstore<L>(Qt + v, tps, czero<L>());
@@ -72,8 +188,10 @@ __global__ __launch_bounds__(NT) void k_eval(EvalArgs<L> a) {
   }
   __syncthreads();
 
-  const int i = blockIdx.x;
-  const int t0 = a.s.offsets[i], t1 = a.s.offsets[i + 1];
+  const int i = blockIdx.x / a.P, part = blockIdx.x - i * a.P;
+  const int m0 = a.s.offsets[i], m1 = a.s.offsets[i + 1];
+  const int chunk = (m1 - m0 + a.P - 1) / a.P;
+  const int t0 = min(m1, m0 + part * chunk), t1 = min(m1, t0 + chunk);
   const int lane = tid & 63, wave = tid >> 6;
   const int grp = lane / LM, gl = lane % LM;
   const int slot = wave * G + grp;
@@ -88,7 +206,15 @@ __global__ __launch_bounds__(NT) void k_eval(EvalArgs<L> a) {
   auto gval = [&](int v, int e) -> C<L> { return v < n ? pload<L>(Gt + (size_t)e * nv + v, tps) : cone<L>(); };
   auto qval = [&](int v, int e) -> C<L> { return v < n ? pload<L>(Qt + (size_t)e * nv + v, tps) : czero<L>(); };
 
-  for (int base = t0; base < t1; base += SLOTS) {
+  if (pw) {
+    if (lane == 0 && a.h.homotopy && a.P == 1) {
+      C<L> pd1, pd;
+      start_powers<L>(x + (size_t)i * 2 * L, a.s.deg[i], pd1, pd);
+      cstore<L>(powbuf, pd1);
+      cstore<L>(powbuf + 2 * L, pd);
+    }
+  }
+  for (int base = t0; base < t1 && !pw; base += SLOTS) {
     const int j = base + slot;
     const bool valid = j < t1;
     const int jj = valid ? j : t0;
@@ -138,7 +264,7 @@ __global__ __launch_bounds__(NT) void k_eval(EvalArgs<L> a) {
 
   // ---- reduction over the monomial groups of a wavefront (fixed butterfly)
 #pragma unroll
-  for (int off = LM; off < 64; off <<= 1) {
+  for (int off = LM; off < 64 && !pw; off <<= 1) {
 #pragma unroll
     for (int k = 0; k < CH; ++k) acc[k] = cadd<L>(acc[k], cshfl_xor<L>(acc[k], off, 64));
     accv = cadd<L>(accv, cshfl_xor<L>(accv, off, 64));
@@ -149,7 +275,7 @@ __global__ __launch_bounds__(NT) void k_eval(EvalArgs<L> a) {
   const size_t rps = (size_t)W * rn;  // plane size of the reduction buffer [W][n+1]
   double *red = smem;
   double *redS = smem + 2 * L * rps;
-  if (lane < LM) {
+  if (lane < LM && !pw) {
 #pragma unroll
     for (int k = 0; k < CH; ++k) {
       const int v = gl + k * LM;
@@ -162,54 +288,104 @@ __global__ __launch_bounds__(NT) void k_eval(EvalArgs<L> a) {
   }
   __syncthreads();
 
-  // ---- fixed-order sum over wavefronts, homotopy blend, store
+  // ---- fixed-order sum over wavefronts; one part: blend and store; several
+  // parts: store this part's row for k_eval_sum
+  if (pw) return;
+  if (a.P == 1) {
+    C<L> pd1 = czero<L>(), pd = cone<L>();
+    if (a.h.homotopy) {
+      pd1 = cload<L>(powbuf);
+      pd = cload<L>(powbuf + 2 * L);
+    }
+    for (int col = tid; col <= n; col += NT) {
+      C<L> s = pload<L>(red + col, rps);
+      for (int w = 1; w < W; ++w) s = cadd<L>(s, pload<L>(red + (size_t)w * rn + col, rps));
+      double S = 0.0;
+      if (col == n)
+        for (int w = 0; w < W; ++w) S += redS[w];
+      eval_finish<L>(a, b, i, col, s, S, pd1, pd);
+    }
+    return;
+  }
+  const size_t rec = part_record(n, L);
+  double *mine = a.part + (((size_t)b * n + i) * a.P + part) * rec;
   for (int col = tid; col <= n; col += NT) {
     C<L> s = pload<L>(red + col, rps);
     for (int w = 1; w < W; ++w) s = cadd<L>(s, pload<L>(red + (size_t)w * rn + col, rps));
-    if (col < n) {
-      C<L> Jv = s;
-      if (a.h.homotopy) {
-        Jv = cmul_d<L>(s, a.h.t);
-        if (col == i) {
-          const C<L> g = cload<L>(a.h.gamma);
-          double e1;
-          R<L> omt = rzero<L>();
-          omt.v[0] = two_sum(1.0, -a.h.t, e1);
-          if (L > 1) omt.v[1] = e1;
-          const C<L> w = cmul_r<L>(g, omt);
-          const int d = a.s.deg[i];
-          const C<L> xi = cload<L>(a.x + (size_t)i * 2 * L);
-          if (d >= 1) {
-            C<L> p1 = cpow<L>(xi, d - 1);
-            Jv = cadd<L>(Jv, cmul<L>(w, cmul_d<L>(p1, (double)d)));
-          }
-        }
-      }
-      pstore<L>(a.o.J + (size_t)i * a.o.rsJ + (size_t)col * a.o.csJ, a.o.psJ, Jv);
-    } else {
-      C<L> hv = s;
-      double S = 0.0;
-      for (int w = 0; w < W; ++w) S += redS[w];
-      if (a.h.homotopy) {
-        const C<L> g = cload<L>(a.h.gamma);
-        double e1;
-        R<L> omt = rzero<L>();
-        omt.v[0] = two_sum(1.0, -a.h.t, e1);
-        if (L > 1) omt.v[1] = e1;
-        const C<L> w = cmul_r<L>(g, omt);
-        const int d = a.s.deg[i];
-        const C<L> xi = cload<L>(a.x + (size_t)i * 2 * L);
-        const C<L> pd = cpow<L>(xi, d);
-        C<L> gm = pd;
-        gm.re = rsub<L>(gm.re, rfrom<L>(1.0));
-        hv = cadd<L>(cmul_d<L>(s, a.h.t), cmul<L>(w, gm));
-        S = fabs(a.h.t) * S + cabs_hi<L>(w) * (cabs_hi<L>(pd) + 1.0);
-      }
-      if (a.o.ysign < 0) hv = cneg<L>(hv);
-      pstore<L>(a.o.y + (size_t)i * a.o.sy, a.o.psy, hv);
-      if (a.o.scale) a.o.scale[i] = S;
-    }
+    cstore<L>(mine + (size_t)col * 2 * L, s);
   }
+  if (tid == 0) {
+    double S = 0.0;
+    for (int w = 0; w < W; ++w) S += redS[w];
+    mine[part_scale_at(n, L)] = S;
+  }
+}
+
+// LDS of the evaluation kernel with NT threads: two power tables of 2L limb
+// planes [emax+1][n rounded up to 32], or the cross-wave reduction buffer of
+// 2L planes [NT/64][n+1] plus NT/64 scale sums, whichever is larger
+inline size_t eval_lds_bytes_nt(int L, const DevSystem &s, int NT) {
+  const size_t nv = ((size_t)s.n + 31) & ~(size_t)31;
+  const size_t tables = 2 * 2 * (size_t)L * (s.emax + 1) * nv;
+  const size_t W = NT / 64;
+  const size_t red = 2 * (size_t)L * W * (s.n + 1) + W;
+  return (tables > red ? tables : red) * sizeof(double);
+}
+
+inline int next_pow2(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+template <int L, int CH, int NT>
+hipError_t launch_eval_lm(int LM, const EvalArgs<L> &a, int B, hipStream_t st) {
+  // the start-power wavefront only when one workgroup finishes its row
+  dim3 grid(a.s.n * a.P, B), block(a.P == 1 && a.h.homotopy ? NT + 64 : NT);
+  const size_t lds = eval_lds_bytes_nt(L, a.s, NT);
+  if (lds > 64 * 1024) {
+    hipError_t e = hipSuccess;
+    switch (LM) {
+#define QDP_ATTR(X)                                                                                   \
+  case X:                                                                                             \
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_eval<L, CH, X, NT>),                    \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                    \
+    break;
+      QDP_ATTR(1) QDP_ATTR(2) QDP_ATTR(4) QDP_ATTR(8) QDP_ATTR(16) QDP_ATTR(32) QDP_ATTR(64)
+#undef QDP_ATTR
+    }
+    if (e != hipSuccess) return e;
+  }
+  switch (LM) {
+#define QDP_LM(X) \
+  case X: hipLaunchKernelGGL((k_eval<L, CH, X, NT>), grid, block, lds, st, a); break;
+    QDP_LM(1) QDP_LM(2) QDP_LM(4) QDP_LM(8) QDP_LM(16) QDP_LM(32) QDP_LM(64)
+#undef QDP_LM
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Launch for one precision: LM lanes per monomial from CH variables per lane;
+// the split P doubles while fewer than 512 workgroups would run and every
+// part keeps at least one wavefront's worth of monomials; 256 threads when
+// four wavefronts cover a part's monomials in one pass, else 512.
+template <int L, int CH>
+hipError_t launch_eval_T(const DevSystem &s, const double *x, long bx, int B, const HomArgs &h, const EvalOut &o,
+                         const NewtonState *gate, const EvalSplit &sp, hipStream_t st) {
+  const int LM = next_pow2((s.n + CH - 1) / CH);
+  if (LM > 64 || B < 1) return hipErrorInvalidValue;
+  const int G = 64 / LM;
+  int P = 1;
+  if (sp.part)
+    while (2 * P <= sp.max_parts && (long)s.n * B * P < 512 && (s.maxm + 2 * P - 1) / (2 * P) >= G) P *= 2;
+  EvalArgs<L> a{s, x, bx, h, o, gate, P, sp.part};
+  const int waves = ((s.maxm + P - 1) / P + G - 1) / G;
+  hipError_t e = waves <= 4 ? launch_eval_lm<L, CH, 256>(LM, a, B, st) : launch_eval_lm<L, CH, 512>(LM, a, B, st);
+  if (e != hipSuccess || P == 1) return e;
+  hipLaunchKernelGGL(k_eval_sum<L>, dim3(s.n, B), dim3(256), 0, st, a);
+  return hipGetLastError();
 }
 
 }  // namespace qdp

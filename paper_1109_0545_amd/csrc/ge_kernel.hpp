@@ -28,13 +28,15 @@
 namespace qdp {
 using namespace mw;
 
+// One workgroup per point of a batch: point b's arrays start b times the
+// per-point size after point 0's.
 template <int L> struct GeArgs {
   int n;
-  double *ab;     // column-major (n+1) x n complex in 2L limb planes: limb c of (r,k) at c*n(n+1) + k*n + r
-  double *scale;  // [n] FP64 componentwise scale of h (nullable -> 1)
-  double *x;      // [n][2][L] current point, updated in place (nullable)
-  double *dz;     // [n][2][L] correction out (nullable)
-  NewtonState *st;
+  double *ab;     // [B] column-major (n+1) x n complex in 2L limb planes: limb c of (r,k) at c*n(n+1) + k*n + r
+  double *scale;  // [B][n] FP64 componentwise scale of h (nullable -> 1)
+  double *x;      // [B][n][2][L] current point, updated in place (nullable)
+  double *dz;     // [B][n][2][L] correction out (nullable)
+  NewtonState *st;  // [B] (nullable)
 };
 
 template <int NT> __device__ double block_max(double v, double *buf) {
@@ -304,9 +306,15 @@ __device__ inline void newton_bookkeeping(NewtonState *s, double rho, bool singu
 
 template <int L, int NT, bool IN_LDS>
 __global__ __launch_bounds__(NT) void k_ge(GeArgs<L> a) {
-  if (a.st && !a.st->active) return;
-  extern __shared__ double smem[];
   const int n = a.n;
+  const size_t b = blockIdx.x;
+  NewtonState *const nst = a.st ? a.st + b : nullptr;
+  if (nst && !nst->active) return;
+  double *const ab = a.ab + b * 2 * L * (size_t)n * (n + 1);
+  const double *const scale = a.scale ? a.scale + b * n : nullptr;
+  double *const xpt = a.x ? a.x + b * n * 2 * L : nullptr;
+  double *const dzp = a.dz ? a.dz + b * n * 2 * L : nullptr;
+  extern __shared__ double smem[];
   const int tid = threadIdx.x, wave = tid >> 6;
   constexpr int E2 = 2 * L;
 
@@ -326,16 +334,16 @@ __global__ __launch_bounds__(NT) void k_ge(GeArgs<L> a) {
   el.perm = el.list1 + n;
   el.ctl = el.perm + n;
 
-  double *M = IN_LDS ? Mlds : a.ab;
+  double *M = IN_LDS ? Mlds : ab;
   const size_t PS = (size_t)n * (n + 1);  // plane size
   if (IN_LDS) {
     const size_t tot = PS * E2;
-    for (size_t q = tid; q < tot; q += NT) Mlds[q] = a.ab[q];
+    for (size_t q = tid; q < tot; q += NT) Mlds[q] = ab[q];
   }
   __syncthreads();
 
   bool bad = false;
-  const double rho = residual_of<L, NT>(M + (size_t)n * n, PS, n, a.scale, redbuf, bad);
+  const double rho = residual_of<L, NT>(M + (size_t)n * n, PS, n, scale, redbuf, bad);
   double pmax = 0.0, pmin = __builtin_inf();
   const bool ok = eliminate<L, NT>(M, PS, n, el, bad, pmax, pmin);
   if (ok && wave == 0)
@@ -346,9 +354,9 @@ __global__ __launch_bounds__(NT) void k_ge(GeArgs<L> a) {
   if (ok) {
     for (int v = tid; v < n; v += NT) {
       const C<L> d = pload<L>(bb + v, n);
-      if (a.dz) cstore<L>(a.dz + (size_t)v * E2, d);
-      if (a.x) {
-        double *xp = a.x + (size_t)v * E2;
+      if (dzp) cstore<L>(dzp + (size_t)v * E2, d);
+      if (xpt) {
+        double *xp = xpt + (size_t)v * E2;
         const C<L> xn = cadd<L>(cload<L>(xp), d);
         cstore<L>(xp, xn);
         xmax = fmax(xmax, cabs1_hi<L>(xn));
@@ -358,7 +366,7 @@ __global__ __launch_bounds__(NT) void k_ge(GeArgs<L> a) {
   }
   dmax = block_max<NT>(dmax, redbuf);
   xmax = block_max<NT>(xmax, redbuf);
-  if (tid == 0 && a.st) newton_bookkeeping(a.st, rho, !ok, bad, dmax, pmax, pmin, xmax);
+  if (tid == 0 && nst) newton_bookkeeping(nst, rho, !ok, bad, dmax, pmax, pmin, xmax);
 }
 
 }  // namespace qdp

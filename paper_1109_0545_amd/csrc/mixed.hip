@@ -34,6 +34,15 @@ struct MixedArgs {
 
 template <int NT, bool IN_LDS>
 __global__ __launch_bounds__(NT) void k_mixed(MixedArgs a) {
+  // point b of a batch: every array advances by its per-point size
+  {
+    const size_t b = blockIdx.x, ps = (size_t)a.n * (a.n + 1);
+    if (a.st) a.st += b;
+    a.ab += b * 4 * ps;
+    if (a.scale) a.scale += b * a.n;
+    if (a.x) a.x += b * a.n * 4;
+    if (a.lu) a.lu += b * 2 * ps;
+  }
   if (a.st && !a.st->active) return;
   extern __shared__ double smem[];
   const int n = a.n;
@@ -175,8 +184,9 @@ size_t mixed_lds_bytes(int n, bool in_lds) {
   return d * sizeof(double) + (3 * (size_t)n + 8) * sizeof(int) + 64;
 }
 
-hipError_t launch_mixed_solve(int n, double *ab, double *scale, double *x, NewtonState *st, double *lu,
+hipError_t launch_mixed_solve(int n, int B, double *ab, double *scale, double *x, NewtonState *st, double *lu,
                               double * /*work*/, int refinements, hipStream_t s) {
+  if (B < 1) return hipErrorInvalidValue;
   constexpr int NT = 1024;
   MixedArgs a{n, ab, scale, x, lu, st, refinements};
   const bool fit = mixed_lds_bytes(n, true) <= 160 * 1024;
@@ -186,12 +196,12 @@ hipError_t launch_mixed_solve(int n, double *ab, double *scale, double *x, Newto
     e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_mixed<NT, true>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_mixed<NT, true>), dim3(1), dim3(NT), lds, s, a);
+    hipLaunchKernelGGL((k_mixed<NT, true>), dim3(B), dim3(NT), lds, s, a);
   } else {
     e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_mixed<NT, false>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_mixed<NT, false>), dim3(1), dim3(NT), lds, s, a);
+    hipLaunchKernelGGL((k_mixed<NT, false>), dim3(B), dim3(NT), lds, s, a);
   }
   return hipGetLastError();
 }

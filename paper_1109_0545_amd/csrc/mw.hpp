@@ -473,14 +473,18 @@ template <int L> MW_DEV void pstore(double *p, size_t ps, const C<L> &a) {
   }
 }
 
-// power x^e for e >= 0 by binary powering
+// power x^e for e >= 0 by binary powering; both products of a step are
+// formed every time (they are independent, so they overlap) and the one the
+// exponent bit does not ask for is dropped
 template <int L> MW_DEV C<L> cpow(const C<L> &x, int e) {
   C<L> r = cone<L>();
   C<L> b = x;
   while (e > 0) {
-    if (e & 1) r = cmul<L>(r, b);
+    const C<L> rb = cmul<L>(r, b);
+    const C<L> bb = cmul<L>(b, b);
+    if (e & 1) r = rb;
+    b = bb;
     e >>= 1;
-    if (e) b = cmul<L>(b, b);
   }
   return r;
 }

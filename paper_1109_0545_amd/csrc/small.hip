@@ -8,8 +8,10 @@ using namespace mw;
 
 // Algorithm 4.1 initialises the residual to 1 and loops while it exceeds eps
 // and fewer than Max_It iterations ran.
-__global__ void k_init_state(NewtonState *s, double eps, int max_it) {
-  if (threadIdx.x != 0) return;
+__global__ void k_init_state(NewtonState *states, int B, double eps, int max_it) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  NewtonState *s = states + b;
   s->iterations = 0;
   s->success = (1.0 < eps) ? 1 : 0;
   s->singular = 0;
@@ -28,8 +30,8 @@ __global__ void k_init_state(NewtonState *s, double eps, int max_it) {
   s->active = (1.0 > eps && max_it > 0) ? 1 : 0;
 }
 
-hipError_t launch_init_state(NewtonState *st, double eps, int max_it, hipStream_t s) {
-  hipLaunchKernelGGL(k_init_state, dim3(1), dim3(64), 0, s, st, eps, max_it);
+hipError_t launch_init_state(NewtonState *st, int B, double eps, int max_it, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_state, dim3((B + 63) / 64), dim3(64), 0, s, st, B, eps, max_it);
   return hipGetLastError();
 }
 

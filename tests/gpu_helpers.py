@@ -37,3 +37,17 @@ def err_over_scale(got_limbs, ref_mpc, scale):
         if scale == 0:
             return 0.0 if d == 0 else float("inf")
         return float(d / scale)
+
+
+def start_power_bounds(L, t, gamma_limbs, x_limbs, d):
+    """Rounding bounds of the start-system terms of the homotopy as the GPU
+    forms them: x^d by binary powering in L limbs takes at most d - 1 roundings'
+    worth of relative error (a rounding made at power k is carried into x^d
+    with weight d/k; summed over the powering chain this is at most d - 1
+    times the error of one complex product), each complex product rounds by
+    at most 4u (u = 2^(-53 L)).  Returns (bound on |error| of (1-t) gamma x^d,
+    bound on |error| of (1-t) gamma d x^(d-1))."""
+    u = 2.0 ** (-53 * L)
+    w = abs(1.0 - t) * abs(complex(float(np.sum(gamma_limbs[0])), float(np.sum(gamma_limbs[1]))))
+    r = abs(complex(float(np.sum(x_limbs[0])), float(np.sum(x_limbs[1]))))
+    return 4.0 * d * u * w * r ** d * 1.01, 4.0 * d * u * w * d * r ** max(d - 1, 0) * 1.01

@@ -9,7 +9,7 @@ import pytest
 from oracle.evaluate import eval_homotopy as o_eval_homotopy
 from oracle.evaluate import eval_system as o_eval_system
 from synth.systems import CONFIGS, config_system, make_system, random_point
-from tests.gpu_helpers import err_over_scale, say
+from tests.gpu_helpers import err_over_scale, say, start_power_bounds
 from tests.oracle_helpers import build, point
 
 pytestmark = pytest.mark.gpu
@@ -125,11 +125,19 @@ def test_eval_homotopy_n32(t):
     y, J, sc = q.eval_homotopy(H, t, x, 2)
     rows = [0, 5, 31]
     ref = o_eval_homotopy(s.exps, s.coefs, s.poly_offsets, s.gamma, t, x, rows=rows, form="quotient")
-    for r, i in enumerate(rows):
-        assert err_over_scale(y[i], ref.y[r], ref.S[r]) <= 1e-30
+    check_homotopy_rows(s, 2, t, x, ref, y, J, sc)
+
+
+def check_homotopy_rows(s, L, t, x, ref, y, J, sc):
+    """tau times the componentwise scale, plus the rounding bound of the
+    start-system power (binary powering in working precision) on h_i and J_ii."""
+    for r, i in enumerate(ref.rows):
+        bv, bd = start_power_bounds(L, t, s.gamma, x[i], int(s.degrees[i]))
+        assert err_over_scale(y[i], ref.y[r], TAU[L] * ref.S[r] + bv) <= 1.0
         assert abs(sc[i] - float(ref.S[r])) <= 1e-12 * float(ref.S[r])
         for v in range(s.n):
-            assert err_over_scale(J[i, v], ref.J[r][v], ref.SJ[r][v]) <= 1e-30
+            extra = bd if v == i else 0.0
+            assert err_over_scale(J[i, v], ref.J[r][v], TAU[L] * ref.SJ[r][v] + extra) <= 1.0
 
 
 def test_eval_dev_variant_matches_host_variant():
@@ -174,3 +182,38 @@ def test_eval_rejects_bad_precision_and_nonfinite():
     with pytest.raises(q.QdpError) as e:
         q.eval_jacobian(S, x, 2)
     assert e.value.status == 4
+
+
+@pytest.mark.parametrize("name,B,rows", [("n8_dd", 5, None), ("n32_dd", 3, [0, 13, 31]), ("n64_dd", 2, [0, 33, 63]),
+                                         ("n64_qd", 2, [7, 63]), ("n128_dd", 1, [0, 127]), ("ragged", 2, [0, 50, 99])])
+def test_eval_homotopy_batch_vs_oracle(name, B, rows):
+    # B points in one launch; the monomials of a polynomial split over several
+    # workgroups (the ragged system: 6 monomials over 4 parts, one part empty)
+    import torch
+
+    import paper_1109_0545_amd as q
+
+    s = make_system(100, 6, 2, 2, 6) if name == "ragged" else config_system(CONFIGS[name])
+    L, t = s.L, 0.43
+    S = q.System.from_synth(s)
+    H = q.Homotopy(S, s.gamma)
+    xs = np.stack([random_point(s.n, L, seed=20 + b, spread=0.05) for b in range(B)])
+    say("eval_homotopy_batch", name, "B", B)
+    stream = torch.cuda.current_stream()
+    xd = torch.from_numpy(xs).cuda()
+    yd = torch.zeros((B, s.n, 2, L), dtype=torch.float64, device="cuda")
+    Jd = torch.zeros((B, s.n, s.n, 2, L), dtype=torch.float64, device="cuda")
+    Sd = torch.zeros((B, s.n), dtype=torch.float64, device="cuda")
+    q.eval_homotopy_batch_dev(H, t, xd, B, L, yd, Jd, Sd, stream=stream)
+    torch.cuda.synchronize()
+    y, J, sc = yd.cpu().numpy(), Jd.cpu().numpy(), Sd.cpu().numpy()
+    for b in range(B):
+        ref = o_eval_homotopy(s.exps, s.coefs, s.poly_offsets, s.gamma, t, xs[b], rows=rows,
+                              form="product" if s.n <= 8 else "quotient")
+        check_homotopy_rows(s, L, t, xs[b], ref, y[b], J[b], sc[b])
+    # the same launch again gives the same bits (fixed-order partial sums)
+    y2 = torch.zeros_like(yd)
+    J2 = torch.zeros_like(Jd)
+    q.eval_homotopy_batch_dev(H, t, xd, B, L, y2, J2, None, stream=stream)
+    torch.cuda.synchronize()
+    assert torch.equal(y2, yd) and torch.equal(J2, Jd)

@@ -28,6 +28,11 @@ def one_step_parity(name, L, t=0.5, form="product", mode=0):
     H = q.Homotopy(S, s.gamma)
     say("newton one step", name, "L", L, "t", t, "mode", mode)
     xg, info = q.newton_step(H, t, x, L, mode=mode, eps=0.0, max_it=1)
+    return check_step(s, x, t, L, xg, info, form)
+
+
+def check_step(s, x, t, L, xg, info, form):
+    """One GPU Newton iteration from x (result xg, info) against the oracle's step."""
     assert info["iterations"] == 1 and not info["success"] and not info["singular"]
     ref = o_newton_step(s.exps, s.coefs, s.poly_offsets, s.gamma, t, x, form=form)
     hs = o_eval_homotopy(s.exps, s.coefs, s.poly_offsets, s.gamma, t, x, form=form)
@@ -187,3 +192,56 @@ def test_residual_sequence_matches_oracle():
         res.append(info["residual_first"])
     for a, b in zip(res, ref):
         assert abs(a - b) <= 1e-6 * b + 1e-29, (res, ref)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_batch_newton_each_point_matches_oracle(mode):
+    # B points in one launch per kernel (evaluation split over workgroups,
+    # one elimination workgroup per point); each point against the oracle
+    import torch
+
+    import paper_1109_0545_amd as q
+
+    name, L, t, B = "n32_dd", 2, 0.5, 3
+    s = config_system(CONFIGS[name])
+    fix = fixture(name)
+    base = [complex(a, b) for a, b in fix["x_half_f64"]]
+    rng = np.random.Generator(np.random.PCG64(5))
+    xs = np.stack([limbs_point([v * (1 + 1e-3 * b * complex(*rng.standard_normal(2))) for v in base], L)
+                   for b in range(B)])
+    S = q.System.from_synth(s)
+    H = q.Homotopy(S, s.gamma)
+    say("newton batch", name, "B", B, "mode", mode)
+    stream = torch.cuda.current_stream()
+    xd = torch.from_numpy(xs).cuda()
+    q.newton_batch_dev(H, t, xd, B, L, mode=mode, eps=0.0, max_it=1, stream=stream)
+    infos = q.last_info_batch(H, L, B, stream=stream)
+    xg = xd.cpu().numpy()
+    for b in range(B):
+        check_step(s, xs[b], t, L, xg[b], infos[b], "quotient")
+
+
+def test_batch_newton_points_run_their_own_loops():
+    # a converged point stops after one iteration while the others continue:
+    # every point's iteration count and success flag equal its single-point run
+    import torch
+
+    import paper_1109_0545_amd as q
+
+    name, L, t = "n32_dd", 2, 1.0
+    s = config_system(CONFIGS[name])
+    fix = fixture(name)
+    zss = [complex(mpc_of(np.array(v))) for v in fix["zss_limbs"]]
+    pts = [limbs_point(zss, L), limbs_point([v * (1 + 1e-4) for v in zss], L),
+           limbs_point([v * (1 + 3e-3j) for v in zss], L)]
+    S = q.System.from_synth(s)
+    H = q.Homotopy(S, s.gamma)
+    say("newton batch loops", name)
+    stream = torch.cuda.current_stream()
+    xd = torch.from_numpy(np.stack(pts)).cuda()
+    q.newton_batch_dev(H, t, xd, len(pts), L, eps=1e-24, max_it=6, stream=stream)
+    infos = q.last_info_batch(H, L, len(pts), stream=stream)
+    single = [q.newton_step(H, t, p, L, eps=1e-24, max_it=6)[1] for p in pts]
+    for a, b in zip(infos, single):
+        assert (a["iterations"], a["success"]) == (b["iterations"], b["success"]), (infos, single)
+    assert infos[0]["success"] and infos[0]["iterations"] < infos[2]["iterations"] <= 6
