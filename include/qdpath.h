@@ -286,7 +286,11 @@ qdp_status qdp_track_path(const qdp_homotopy *h, double *x, qdp_prec prec, const
  * count elements on the GPU (device pointers, asynchronous).  Real ops take
  * [L] doubles per element, complex ops [2][L].
  * op: 0 add, 1 sub, 2 mul, 3 div (real); 10 cadd, 11 csub, 12 cmul, 13 cdiv,
- *     14 cfms (a - b*c), 15 cinv (1/a). */
+ *     14 cfms (a - b*c), 15 cinv (1/a);
+ *     16 the elimination's pivot search: a complex, count a multiple of 64; for
+ *        each group of 64, out[i][0] = index in the group of the largest
+ *        |Re| + |Im| of the leading limbs (keys equal in their leading 32 bits
+ *        tie, the lowest index wins; -1 when every key is zero or NaN). */
 qdp_status qdp_arith_batch(int32_t op, qdp_prec prec, int64_t count, const double *a, const double *b,
                            const double *c, double *out, void *hip_stream);
 

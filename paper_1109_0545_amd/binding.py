@@ -24,7 +24,7 @@ PRED_SECANT, PRED_LEARNED, PRED_QUADRATIC = 0, 1, 2
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENONFINITE", 5: "EUNSUPPORTED"}
 
 ARITH_OPS = {"add": 0, "sub": 1, "mul": 2, "div": 3, "cadd": 10, "csub": 11, "cmul": 12, "cdiv": 13, "cfms": 14,
-             "cinv": 15}
+             "cinv": 15, "pivot": 16}
 
 
 class QdpError(RuntimeError):
@@ -428,8 +428,8 @@ def arith_batch(op: str, prec: int, a, b=None, c=None, stream=None):
     """Elementwise multiword op on device tensors (float64, [count][L] or [count][2][L])."""
     import torch
 
-    out = torch.empty_like(a)
     count = a.shape[0]
+    out = torch.empty((count, prec), dtype=a.dtype, device=a.device) if op == "pivot" else torch.empty_like(a)
     _check(lib().qdp_arith_batch(ARITH_OPS[op], prec, count, _ptr(a), _ptr(b), _ptr(c), _ptr(out),
                                  _stream(stream)))
     return out

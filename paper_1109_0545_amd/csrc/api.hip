@@ -864,10 +864,11 @@ extern "C" qdp_status qdp_arith_batch(int32_t op, qdp_prec prec, int64_t count, 
   const int L = (int)prec;
   if (!valid_prec(L)) return fail(QDP_EINVAL, "prec must be 1, 2 or 4");
   if (count < 0 || !a || !out) return fail(QDP_EINVAL, "bad arguments");
-  const bool binary = !(op == 15);
+  const bool binary = !(op == 15 || op == 16);
   if (binary && !b) return fail(QDP_EINVAL, "b is NULL");
   if (op == 14 && !c) return fail(QDP_EINVAL, "c is NULL");
-  if (!((op >= 0 && op <= 3) || (op >= 10 && op <= 15))) return fail(QDP_EINVAL, "unknown op");
+  if (!((op >= 0 && op <= 3) || (op >= 10 && op <= 16))) return fail(QDP_EINVAL, "unknown op");
+  if (op == 16 && count % 64 != 0) return fail(QDP_EINVAL, "the pivot search works on groups of 64");
   if (count == 0) return QDP_OK;
   HIPCHK(qdp::launch_arith(op, L, count, a, b, c, out, (hipStream_t)stream));
   return QDP_OK;

@@ -66,13 +66,42 @@ __device__ inline unsigned long long pack_key(double key, int row) {
 __device__ inline int unpack_row(unsigned long long w) { return 0x7fffffff - (int)(w & 0xffffffffu); }
 __device__ inline bool packed_nonzero(unsigned long long w) { return (w >> 32) > 1u; }
 
+// One butterfly step of a wavefront maximum on a 64-bit key: each lane takes
+// the larger of its key and the key of the lane the DPP control names.
+template <int CTRL> __device__ inline unsigned long long dpp_max_step(unsigned long long w) {
+  const int lo = (int)(unsigned)w, hi = (int)(unsigned)(w >> 32);
+  const unsigned olo = (unsigned)__builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
+  const unsigned ohi = (unsigned)__builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
+  const unsigned long long o = ((unsigned long long)ohi << 32) | olo;
+  return o > w ? o : w;
+}
+
+// Maximum over a full wavefront (all 64 lanes active), returned in every
+// lane: butterflies inside each row of 16 lanes with DPP (lane xor 1, lane
+// xor 2, the half-row mirror, the row mirror), then the four row maxima read
+// into scalars.  No LDS round trip.
 __device__ inline unsigned long long wave_max_u64(unsigned long long w) {
+  w = dpp_max_step<0xB1>(w);   // quad_perm [1,0,3,2]
+  w = dpp_max_step<0x4E>(w);   // quad_perm [2,3,0,1]
+  w = dpp_max_step<0x141>(w);  // row_half_mirror
+  w = dpp_max_step<0x140>(w);  // row_mirror
+  unsigned long long m = 0;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const unsigned long long ow = __shfl_xor(w, o, 64);
-    w = ow > w ? ow : w;
+  for (int r = 0; r < 4; ++r) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)w, 16 * r);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(w >> 32), 16 * r);
+    const unsigned long long v = ((unsigned long long)hi << 32) | lo;
+    m = v > m ? v : m;
   }
-  return w;
+  return m;
+}
+
+// value of lane `src` (the same in every lane) in every lane
+__device__ inline double rdlane(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, src);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), src);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
 // broadcast lane `src` (wave-uniform) of a complex multiword value
@@ -80,8 +109,8 @@ template <int L> __device__ inline C<L> cbcast(const C<L> &a, int src) {
   C<L> r;
 #pragma unroll
   for (int k = 0; k < L; ++k) {
-    r.re.v[k] = __shfl(a.re.v[k], src, 64);
-    r.im.v[k] = __shfl(a.im.v[k], src, 64);
+    r.re.v[k] = rdlane(a.re.v[k], src);
+    r.im.v[k] = rdlane(a.im.v[k], src);
   }
   return r;
 }
@@ -94,6 +123,10 @@ template <int L> struct ElimLds {
   int *ctl;    // [4] parity-indexed control words (see eliminate)
 };
 
+// rows of the matrix a lane of wavefront 0 owns: lane + 64 u, u < RPL; RPL = 1
+// for n <= 64 keeps the look-ahead state small, 4 covers n <= 256
+constexpr int kRowsPerLane = 4;
+
 // Gaussian elimination with partial pivoting of the column-major matrix M
 // (n rows, n+1 columns, 2L limb planes PS apart), one workgroup of NT
 // threads; the last column is the right-hand side and is eliminated too.
@@ -101,47 +134,95 @@ template <int L> struct ElimLds {
 // pivot row of column j and invp[j] the inverse of its pivot.  Returns false
 // when a column has no nonzero pivot.  Must be called by every thread.
 //
-// Wavefront 0 looks one column ahead: during step j it updates column j+1 of
-// every remaining row, finds that column's pivot (largest |Re|+|Im| of the
-// leading limb; see pack_key), forms its inverse and stores the multipliers
-// of column j+1, and publishes pivot row / list slot / inverse / singular
-// flag in parity-indexed LDS words (ctl[j & 1] = slot of the pivot of column
-// j in the list of step j, ctl[2 + (j & 1)] = column j has no nonzero pivot),
-// while the other wavefronts update columns j+2..n.  One barrier per column.
-template <int L, int NT>
+// Wavefront 0 looks one column ahead and keeps its state in registers: lane l
+// owns rows l + 64u with an "not yet pivot" flag and the multiplier of the
+// last pivot column.  During step j it updates column j+1 of its rows, finds
+// that column's pivot (largest |Re|+|Im| of the leading limb; see pack_key)
+// with a DPP maximum, forms the pivot's inverse, stores the multipliers of
+// column j+1 and writes the list of rows the next step updates, while the
+// other wavefronts update columns j+2..n of the rows of this step's list.
+// Pivot row, inverse and a singular flag go to LDS (parity-indexed: ctl[2 +
+// (j & 1)] = column j has no nonzero pivot).  One barrier per column.
+template <int L, int NT, int RPL = kRowsPerLane>
 __device__ bool eliminate(double *M, size_t PS, int n, const ElimLds<L> &e, bool bad, double &pmax, double &pmin) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   auto at = [&](int r, int k) -> double * { return M + (size_t)k * n + r; };
   C<L> *invp = e.invp;
   int *perm = e.perm, *ctl = e.ctl;
-  for (int r = tid; r < n; r += NT) e.list0[r] = r;
+  const unsigned long long below = (1ull << lane) - 1ull;  // lanes under this one
+
+  bool act[RPL];    // wavefront 0: row lane + 64u not yet a pivot row
+  C<L> mul[RPL];    // wavefront 0: its multiplier of the last pivot column
+  int p = 0;        // wavefront 0: pivot row of the current column
+
+  // wavefront 0, after the pivot p1 of a column is chosen among the values v:
+  // multipliers (or, for the pivot row, the U entry) stored in column k,
+  // flags updated, and the ordered list of the remaining rows written to out
+  auto publish = [&](C<L> (&v)[RPL], int k, int p1, bool sing, const C<L> &inv, int *out) {
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) {
+      if (64 * u >= n) break;  // wave-uniform: no row in this slot
+      const int r = lane + 64 * u;
+      if (act[u]) {
+        if (r == p1) {
+          pstore<L>(at(r, k), PS, v[u]);
+          act[u] = false;
+        } else if (!sing) {
+          mul[u] = cmul<L>(v[u], inv);
+          pstore<L>(at(r, k), PS, mul[u]);
+        }
+      }
+    }
+    int base = 0;
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) {
+      if (64 * u >= n) break;
+      const unsigned long long m = __ballot(act[u]);
+      if (act[u]) out[base + __popcll(m & below)] = lane + 64 * u;
+      base += __popcll(m);
+    }
+  };
+  // the pivot row's value, from the lane that holds it (a per-lane select,
+  // not an index into v: an indexed register array would go to scratch)
+  auto pivot_value = [&](C<L> (&v)[RPL], int p1) {
+    C<L> pv = czero<L>();
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) pv = cselect<L>(lane + 64 * u == p1, v[u], pv);
+    return cbcast<L>(pv, p1 & 63);
+  };
+
+  // wavefront 0 carries the column-to-column dependence chain: it issues
+  // first when the SIMD it shares with update wavefronts has a choice
+  if (wave == 0) __builtin_amdgcn_s_setprio(3);
 
   // ---- column 0: pivot and multipliers (wavefront 0)
   if (wave == 0) {
     unsigned long long best = 0;
-    for (int s = lane; s < n; s += 64) {
-      const unsigned long long w = pack_key(cabs1_hi<L>(pload<L>(at(s, 0), PS)), s);
-      best = w > best ? w : best;
+    C<L> v[RPL];
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) {
+      const int r = lane + 64 * u;
+      act[u] = r < n;
+      v[u] = czero<L>();
+      if (act[u]) {
+        v[u] = pload<L>(at(r, 0), PS);
+        const unsigned long long w = pack_key(cabs1_hi<L>(v[u]), r);
+        best = w > best ? w : best;
+      }
     }
     best = wave_max_u64(best);
     const bool sing = !packed_nonzero(best) || bad;
-    const int p0 = unpack_row(best);
-    if (!sing) {
-      const C<L> pv = pload<L>(at(p0, 0), PS);
-      const C<L> inv = cinv<L>(pv);
-      for (int s = lane; s < n; s += 64)
-        if (s != p0) pstore<L>(at(s, 0), PS, cmul<L>(pload<L>(at(s, 0), PS), inv));
-      if (lane == 0) {
-        invp[0] = inv;
-        const double k = cabs1_hi<L>(pv);
-        pmax = k;
-        pmin = k;
-      }
-    }
+    p = unpack_row(best);
+    const C<L> pv = pivot_value(v, p);
+    const C<L> inv = sing ? czero<L>() : cinv<L>(pv);
+    publish(v, 0, p, sing, inv, e.list0);
     if (lane == 0) {
+      invp[0] = inv;
+      const double k = cabs1_hi<L>(pv);
+      pmax = k;
+      pmin = k;
       ctl[2] = sing ? 1 : 0;
-      ctl[0] = p0;  // the initial list is the identity: slot = row
-      perm[0] = p0;
+      perm[0] = p;
     }
   }
   __syncthreads();
@@ -150,74 +231,43 @@ __device__ bool eliminate(double *M, size_t PS, int n, const ElimLds<L> &e, bool
   bool singular = ctl[2] != 0;
   int steps_done = 0;
   for (int j = 0; j < n && !singular; ++j) {
-    const int K = n - j;  // rows in the list (the pivot row included)
-    const int R = K - 1;  // rows to update
-    const int p = perm[j];
-    const int pos = ctl[j & 1];
-    // slot s of the rows to update -> row (the list without the pivot, order kept)
-    auto row_of = [&](int s) { return cur[s + (s >= pos ? 1 : 0)]; };
+    const int R = n - 1 - j;  // rows this step updates: not yet pivot rows
     if (R > 0) {
       if (wave == 0) {
-        // look-ahead: update column j+1, choose its pivot, store its multipliers
+        // look-ahead: column j+1 of every remaining row, its pivot, multipliers
         const C<L> up = pload<L>(at(p, j + 1), PS);
         unsigned long long best = 0;
-        constexpr int RPL = 4;  // rows per lane kept in registers (n <= 256)
-        C<L> vals[RPL];
-        int rows[RPL];
+        C<L> v[RPL];
 #pragma unroll
         for (int u = 0; u < RPL; ++u) {
-          const int s = lane + 64 * u;
-          rows[u] = -1;
-          vals[u] = czero<L>();
-          if (s < R) {
-            const int r = row_of(s);
-            const C<L> v = cfms<L>(pload<L>(at(r, j + 1), PS), pload<L>(at(r, j), PS), up);
-            vals[u] = v;
-            rows[u] = r;
-            nxt[s] = r;
-            const unsigned long long w = pack_key(cabs1_hi<L>(v), r);
+          const int r = lane + 64 * u;
+          v[u] = czero<L>();
+          if (64 * u < n && act[u]) {
+            v[u] = cfms<L>(pload<L>(at(r, j + 1), PS), mul[u], up);
+            const unsigned long long w = pack_key(cabs1_hi<L>(v[u]), r);
             best = w > best ? w : best;
           }
         }
         best = wave_max_u64(best);
         const bool sing = !packed_nonzero(best);
         const int p1 = unpack_row(best);
-        // the lane holding the pivot value broadcasts it
-        int owner = 0, ou = 0;
-#pragma unroll
-        for (int u = 0; u < RPL; ++u) {
-          const unsigned long long m = __ballot(rows[u] == p1);
-          if (m) {
-            owner = __builtin_ffsll(m) - 1;
-            ou = u;
-          }
-        }
-        C<L> pv = vals[0];
-#pragma unroll
-        for (int u = 1; u < RPL; ++u)
-          if (ou == u) pv = vals[u];
-        pv = cbcast<L>(pv, owner);
-        if (!sing) {
-          const C<L> inv = cinv<L>(pv);
-#pragma unroll
-          for (int u = 0; u < RPL; ++u)
-            if (rows[u] >= 0) pstore<L>(at(rows[u], j + 1), PS, rows[u] == p1 ? vals[u] : cmul<L>(vals[u], inv));
-          if (lane == 0) {
-            invp[j + 1] = inv;
-            const double k = cabs1_hi<L>(pv);
-            pmax = fmax(pmax, k);
-            pmin = fmin(pmin, k);
-          }
-        }
+        const C<L> pv = pivot_value(v, p1);
+        const C<L> inv = sing ? czero<L>() : cinv<L>(pv);
+        publish(v, j + 1, p1, sing, inv, nxt);
         if (lane == 0) {
+          invp[j + 1] = inv;
+          const double k = cabs1_hi<L>(pv);
+          pmax = fmax(pmax, k);
+          pmin = fmin(pmin, k);
           ctl[2 + ((j + 1) & 1)] = sing ? 1 : 0;
-          ctl[(j + 1) & 1] = ou * 64 + owner;
           perm[j + 1] = p1;
         }
+        p = p1;
       } else {
         // trailing update of columns j+2..n: items (column, row slot) in
         // column-major order spread evenly over wavefronts 1..
         const int ncol = n - j - 1;
+        const int pj = perm[j];
         if (ncol > 0) {
           constexpr int T = NT - 64;
           const int items = R * ncol;
@@ -225,16 +275,33 @@ __device__ bool eliminate(double *M, size_t PS, int n, const ElimLds<L> &e, bool
           if (t < items) {
             const int dk = T / R, ds = T - dk * R;
             int s = t % R, k = j + 2 + t / R;
-            for (int q = t; q < items; q += T) {
-              const int r = row_of(s);
-              double *ep = at(r, k);
-              pstore<L>(ep, PS, cfms<L>(pload<L>(ep, PS), pload<L>(at(r, j), PS), pload<L>(at(p, k), PS)));
-              s += ds;
-              k += dk;
-              if (s >= R) {
-                s -= R;
-                k += 1;
+            // UN items per round with every load issued before the arithmetic
+            // (independent items: the loads overlap, which matters when the
+            // matrix lives in global memory)
+            constexpr int UN = 2;
+            for (int q = t; q < items; q += UN * T) {
+              double *ep[UN];
+              C<L> av[UN], lv[UN], uv[UN];
+#pragma unroll
+              for (int w = 0; w < UN; ++w) {
+                ep[w] = nullptr;
+                if (q + w * T < items) {
+                  const int r = cur[s];
+                  ep[w] = at(r, k);
+                  av[w] = pload<L>(ep[w], PS);
+                  lv[w] = pload<L>(at(r, j), PS);
+                  uv[w] = pload<L>(at(pj, k), PS);
+                }
+                s += ds;
+                k += dk;
+                if (s >= R) {
+                  s -= R;
+                  k += 1;
+                }
               }
+#pragma unroll
+              for (int w = 0; w < UN; ++w)
+                if (ep[w]) pstore<L>(ep[w], PS, cfms<L>(av[w], lv[w], uv[w]));
             }
           }
         }
@@ -247,27 +314,49 @@ __device__ bool eliminate(double *M, size_t PS, int n, const ElimLds<L> &e, bool
     cur = nxt;
     nxt = tmp;
   }
+  if (wave == 0) __builtin_amdgcn_s_setprio(0);
   return !singular && steps_done == n;
 }
 
 // Back substitution by wavefront 0 on the eliminated matrix: returns through
 // the limb planes of `out` (n elements, plane stride n) the solution of the
 // upper triangle (rows perm[0..n-1]) with right-hand side rhs_of(i) for the
-// pivot-ordered index i.
-template <int L, typename Rhs>
+// pivot-ordered index i.  Lane l keeps entries l + 64u in registers; each
+// column's solution value travels by lane reads, not LDS.
+template <int L, typename Rhs, int RPL = kRowsPerLane>
 __device__ void back_substitute(const double *M, size_t PS, int n, const int *perm, const C<L> *invp, double *out,
                                 Rhs rhs_of) {
   const int lane = threadIdx.x & 63;
   auto at = [&](int r, int k) -> const double * { return M + (size_t)k * n + r; };
-  for (int i = lane; i < n; i += 64) pstore<L>(out + i, n, rhs_of(i));
+  C<L> b[RPL];
+  int pr[RPL];
+#pragma unroll
+  for (int u = 0; u < RPL; ++u) {
+    const int i = lane + 64 * u;
+    b[u] = czero<L>();
+    pr[u] = 0;
+    if (i < n) {
+      b[u] = rhs_of(i);
+      pr[u] = perm[i];
+    }
+  }
   for (int j = n - 1; j >= 0; --j) {
-    const int owner = j & 63;
-    C<L> dj = czero<L>();
-    if (lane == owner) dj = cmul<L>(pload<L>(out + j, n), invp[j]);
-    dj = cbcast<L>(dj, owner);
-    for (int i = lane; i < j; i += 64)
-      pstore<L>(out + i, n, cfms<L>(pload<L>(out + i, n), pload<L>(at(perm[i], j), PS), dj));
-    if (lane == owner) pstore<L>(out + j, n, dj);
+    C<L> bj = czero<L>();
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) bj = cselect<L>(lane + 64 * u == j, b[u], bj);
+    const C<L> dj = cmul<L>(cbcast<L>(bj, j & 63), invp[j]);
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) {
+      if (64 * u > j) break;  // wave-uniform: no row of this slot is at or above j
+      const int i = lane + 64 * u;
+      if (i < j) b[u] = cfms<L>(b[u], pload<L>(at(pr[u], j), PS), dj);
+      else if (i == j) b[u] = dj;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < RPL; ++u) {
+    const int i = lane + 64 * u;
+    if (i < n) pstore<L>(out + i, n, b[u]);
   }
 }
 
@@ -304,7 +393,7 @@ __device__ inline void newton_bookkeeping(NewtonState *s, double rho, bool singu
   s->active = (!singular && rho > s->eps && s->iterations < s->max_it) ? 1 : 0;
 }
 
-template <int L, int NT, bool IN_LDS>
+template <int L, int NT, bool IN_LDS, int RPL>
 __global__ __launch_bounds__(NT) void k_ge(GeArgs<L> a) {
   const int n = a.n;
   const size_t b = blockIdx.x;
@@ -345,10 +434,9 @@ __global__ __launch_bounds__(NT) void k_ge(GeArgs<L> a) {
   bool bad = false;
   const double rho = residual_of<L, NT>(M + (size_t)n * n, PS, n, scale, redbuf, bad);
   double pmax = 0.0, pmin = __builtin_inf();
-  const bool ok = eliminate<L, NT>(M, PS, n, el, bad, pmax, pmin);
-  if (ok && wave == 0)
-    back_substitute<L>(M, PS, n, el.perm, el.invp, bb,
-                       [&](int i) { return pload<L>(M + (size_t)n * n + el.perm[i], PS); });
+  const bool ok = eliminate<L, NT, RPL>(M, PS, n, el, bad, pmax, pmin);
+  auto rhs = [&](int i) { return pload<L>(M + (size_t)n * n + el.perm[i], PS); };
+  if (ok && wave == 0) back_substitute<L, decltype(rhs), RPL>(M, PS, n, el.perm, el.invp, bb, rhs);
   __syncthreads();
   double dmax = 0.0, xmax = 0.0;
   if (ok) {

@@ -364,7 +364,13 @@ template <int L> MW_DEV C<L> cinv(const C<L> &a) {
   if (m > 0.0 && m < __builtin_inf()) (void)frexp(m, &ex);
   const C<L> p{rldexp<L>(a.re, -ex), rldexp<L>(a.im, -ex)};
   const double pr = p.re.v[0], pi = p.im.v[0];
-  const double r0 = 1.0 / __builtin_fma(pr, pr, pi * pi);
+  // 1/|p|^2 with |p| in [1/2, sqrt 2): the hardware reciprocal estimate and two
+  // FP64 Newton steps (each squares the relative error, down to FP64 rounding;
+  // the double-double correction below squares what is left)
+  const double q2 = __builtin_fma(pr, pr, pi * pi);
+  double r0 = __builtin_amdgcn_rcp(q2);
+  r0 = __builtin_fma(r0, __builtin_fma(-q2, r0, 1.0), r0);
+  r0 = __builtin_fma(r0, __builtin_fma(-q2, r0, 1.0), r0);
   const double i0r = pr * r0, i0i = -pi * r0;
   C<L> inv;
   if constexpr (L == 1) {

@@ -2,6 +2,7 @@
 // and the multiword arithmetic test entry.
 
 #include "common.hpp"
+#include "ge_kernel.hpp"
 
 namespace qdp {
 using namespace mw;
@@ -142,7 +143,16 @@ hipError_t launch_copy(double *dst, const double *src, size_t count, hipStream_t
 template <int L>
 __global__ void k_arith(int op, int64_t count, const double *a, const double *b, const double *c, double *out) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= count) return;
+  if (q >= count) return;  // count is a multiple of 64 for op 16: whole wavefronts stay
+  if (op == 16) {
+    // the elimination's pivot search over each group of 64 elements (one wavefront)
+    const C<L> x = cload<L>(a + q * 2 * L);
+    const unsigned long long best = wave_max_u64(pack_key(cabs1_hi<L>(x), (int)(threadIdx.x & 63)));
+    out[q * L] = packed_nonzero(best) ? (double)unpack_row(best) : -1.0;
+#pragma unroll
+    for (int k = 1; k < L; ++k) out[q * L + k] = 0.0;
+    return;
+  }
   if (op < 10) {
     R<L> x, y, r;
 #pragma unroll

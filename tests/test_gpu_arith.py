@@ -100,3 +100,36 @@ def test_zero_and_exact_cases(L):
     assert np.all(out == one)
     out = _run("cinv", L, one)
     assert np.all(out == one)
+
+
+@pytest.mark.parametrize("L", [1, 2, 4])
+def test_pivot_search_matches_argmax(L):
+    # the wavefront maximum the elimination uses to pick pivots: per group of
+    # 64, the index of the largest |Re| + |Im| of the leading limbs, compared
+    # on the high 32 bits of that FP64 value, ties to the lowest index
+    import torch
+
+    import paper_1109_0545_amd as q
+
+    rng = np.random.Generator(np.random.PCG64(40 + L))
+    groups = 60
+    a = np.zeros((groups * 64, 2, L))
+    a[:, :, 0] = rng.standard_normal((groups * 64, 2)) * np.exp(rng.uniform(-30, 30, (groups * 64, 1)))
+    a[:64, :, 0] = 1.0                      # all equal: index 0
+    a[64:128, :, 0] = 0.0                   # all zero: no pivot
+    a[64 + 17, 0, 0] = -3e-300              # one tiny nonzero: index 17
+    a[128:192, :, 0] = rng.uniform(0.5, 1.0, (64, 2))
+    a[128 + 40] = a[128 + 5] = [[7.0] + [0.0] * (L - 1), [-2.0] + [0.0] * (L - 1)]  # tie: 5
+    a[192 + 63, 1, 0] = 1e300                # the last lane
+    say("pivot search L", L)
+    out = q.arith_batch("pivot", L, torch.from_numpy(a).cuda()).cpu().numpy()[:, 0]
+    key = np.abs(a[:, 0, 0]) + np.abs(a[:, 1, 0])
+    hi = (key.view(np.uint64) >> np.uint64(32)).reshape(groups, 64)
+    for g in range(groups):
+        got = out[g * 64: (g + 1) * 64]
+        assert np.all(got == got[0])  # every lane holds the group's answer
+        if np.all(key[g * 64: (g + 1) * 64] == 0):
+            assert got[0] == -1
+        else:
+            assert got[0] == int(np.flatnonzero(hi[g] == hi[g].max())[0]), g
+    assert out[0] == 0 and out[64] == 17 and out[128] == 5 and out[192] == 63
