@@ -264,44 +264,36 @@ __device__ bool eliminate(double *M, size_t PS, int n, const ElimLds<L> &e, bool
         }
         p = p1;
       } else {
-        // trailing update of columns j+2..n: items (column, row slot) in
-        // column-major order spread evenly over wavefronts 1..
+        // trailing update of columns j+2..n: each thread keeps one row (and
+        // its multiplier) and takes every CPR-th column, two at a time with
+        // both loads issued first; lanes of a wavefront share columns, so the
+        // pivot row's entry is a broadcast read
         const int ncol = n - j - 1;
         const int pj = perm[j];
         if (ncol > 0) {
           constexpr int T = NT - 64;
-          const int items = R * ncol;
           const int t = tid - 64;
-          if (t < items) {
-            const int dk = T / R, ds = T - dk * R;
-            int s = t % R, k = j + 2 + t / R;
-            // UN items per round with every load issued before the arithmetic
-            // (independent items: the loads overlap, which matters when the
-            // matrix lives in global memory)
+          const int CPR = T / R;
+          if (t < CPR * R) {
+            const int sl = t % R, c = t / R;
+            const int r = cur[sl];
+            const C<L> lr = pload<L>(at(r, j), PS);
             constexpr int UN = 2;
-            for (int q = t; q < items; q += UN * T) {
-              double *ep[UN];
-              C<L> av[UN], lv[UN], uv[UN];
+            for (int k = j + 2 + c; k <= n; k += UN * CPR) {
+              C<L> av[UN], uv[UN];
 #pragma unroll
               for (int w = 0; w < UN; ++w) {
-                ep[w] = nullptr;
-                if (q + w * T < items) {
-                  const int r = cur[s];
-                  ep[w] = at(r, k);
-                  av[w] = pload<L>(ep[w], PS);
-                  lv[w] = pload<L>(at(r, j), PS);
-                  uv[w] = pload<L>(at(pj, k), PS);
-                }
-                s += ds;
-                k += dk;
-                if (s >= R) {
-                  s -= R;
-                  k += 1;
+                const int kk = k + w * CPR;
+                if (kk <= n) {
+                  av[w] = pload<L>(at(r, kk), PS);
+                  uv[w] = pload<L>(at(pj, kk), PS);
                 }
               }
 #pragma unroll
-              for (int w = 0; w < UN; ++w)
-                if (ep[w]) pstore<L>(ep[w], PS, cfms<L>(av[w], lv[w], uv[w]));
+              for (int w = 0; w < UN; ++w) {
+                const int kk = k + w * CPR;
+                if (kk <= n) pstore<L>(at(r, kk), PS, cfms<L>(av[w], lr, uv[w]));
+              }
             }
           }
         }
