@@ -4,8 +4,11 @@
 
 namespace qdp {
 
+// Past 64 variables, eight per lane (fewer lanes per monomial, so fewer scan
+// steps; measured faster at n = 128, slower at n = 64).
 hipError_t launch_eval_dd(const DevSystem &s, const double *x, long bx, int B, const HomArgs &h, const EvalOut &o,
                          const NewtonState *gate, const EvalSplit &sp, hipStream_t st) {
+  if (s.n > 64) return launch_eval_T<2, 8>(s, x, bx, B, h, o, gate, sp, st);
   return launch_eval_T<2, 4>(s, x, bx, B, h, o, gate, sp, st);
 }
 

@@ -382,7 +382,9 @@ hipError_t launch_eval_T(const DevSystem &s, const double *x, long bx, int B, co
     while (2 * P <= sp.max_parts && (long)s.n * B * P < 512 && (s.maxm + 2 * P - 1) / (2 * P) >= G) P *= 2;
   EvalArgs<L> a{s, x, bx, h, o, gate, P, sp.part};
   const int waves = ((s.maxm + P - 1) / P + G - 1) / G;
-  hipError_t e = waves <= 4 ? launch_eval_lm<L, CH, 256>(LM, a, B, st) : launch_eval_lm<L, CH, 512>(LM, a, B, st);
+  // eight variables per lane need ~220 registers: 256 threads (+ the power wavefront) only
+  hipError_t e = (CH >= 8 && L >= 2) || waves <= 4 ? launch_eval_lm<L, CH, 256>(LM, a, B, st)
+                                                   : launch_eval_lm<L, CH, 512>(LM, a, B, st);
   if (e != hipSuccess || P == 1) return e;
   hipLaunchKernelGGL(k_eval_sum<L>, dim3(s.n, B), dim3(256), 0, st, a);
   return hipGetLastError();

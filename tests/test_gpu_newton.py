@@ -245,3 +245,20 @@ def test_batch_newton_points_run_their_own_loops():
     for a, b in zip(infos, single):
         assert (a["iterations"], a["success"]) == (b["iterations"], b["success"]), (infos, single)
     assert infos[0]["success"] and infos[0]["iterations"] < infos[2]["iterations"] <= 6
+
+
+@pytest.mark.parametrize("n,L", [(1, 2), (12, 4), (40, 1), (64, 1)])
+def test_one_step_small_systems(n, L):
+    # edge shapes of the elimination: n = 1 (no pivot chain), quad double
+    # with the matrix in LDS, FP64 up to n = 64
+    import paper_1109_0545_amd as q
+    from synth.systems import make_system, random_point
+
+    s = make_system(n, 3 if n == 1 else 6, 2, max(L, 2), 30 + n)
+    s = s.truncated(L) if L < s.L else s
+    x = random_point(n, L, seed=31 + n, spread=0.1)
+    S = q.System.from_synth(s)
+    H = q.Homotopy(S, s.gamma)
+    say("newton small system n", n, "L", L)
+    xg, info = q.newton_step(H, 0.3, x, L, eps=0.0, max_it=1)
+    check_step(s, x, 0.3, L, xg, info, "product" if n <= 12 else "quotient")
