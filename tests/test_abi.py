@@ -83,3 +83,14 @@ def test_errors_are_reported_without_gpu_work():
     with pytest.raises(q.QdpError) as e:
         q.System(1, np.array([0, 1], np.int32), np.zeros((1, 1), np.uint8), np.zeros((1, 2, 3)), 3)
     assert e.value.status == 1
+
+
+def test_batch_entry_points_reject_null_arguments():
+    # errors found before any GPU work: NULL handles and buffers
+    from paper_1109_0545_amd import binding as B
+
+    lib = B.lib()
+    assert lib.qdp_newton_batch_dev(None, 0.5, None, 4, 2, 0, 1e-10, 4, None) == 1
+    assert lib.qdp_eval_homotopy_batch_dev(None, 0.5, None, 1, 2, None, None, None, None) == 1
+    assert lib.qdp_homotopy_last_info_batch(None, 2, 1, None, None) == 1
+    assert b"NULL" in lib.qdp_last_error()

@@ -262,3 +262,28 @@ def test_one_step_small_systems(n, L):
     say("newton small system n", n, "L", L)
     xg, info = q.newton_step(H, 0.3, x, L, eps=0.0, max_it=1)
     check_step(s, x, 0.3, L, xg, info, "product" if n <= 12 else "quotient")
+
+
+@pytest.mark.parametrize("n,L", [(200, 2), (100, 4), (256, 1)])
+def test_newton_converges_at_large_n(n, L):
+    # beyond the oracle's reach: from a point near the planted root of a
+    # system at t = 1, the Newton loop must converge (residual below the
+    # working precision's floor within a few iterations, quadratically);
+    # covers the elimination with four (n > 128) and two rows per lane and
+    # quad double with the matrix in global memory
+    import paper_1109_0545_amd as q
+    from synth.systems import make_system
+
+    s = make_system(n, 12, 2, max(L, 2), 50 + n)
+    s = s.truncated(L) if L < s.L else s
+    rng = np.random.Generator(np.random.PCG64(n))
+    x = np.zeros((n, 2, L))
+    x[:, :, 0] = s.zstar[:, :, 0] * (1.0 + 1e-7 * rng.standard_normal((n, 1)))
+    S = q.System.from_synth(s)
+    H = q.Homotopy(S, s.gamma)
+    say("newton large n", n, "L", L)
+    eps = {1: 1e-12, 2: 1e-26, 4: 1e-55}[L]
+    xg, info = q.newton_step(H, 1.0, x, L, eps=eps, max_it=8)
+    assert info["success"] and not info["singular"] and info["iterations"] <= 6, info
+    _, info2 = q.newton_step(H, 1.0, xg, L, eps=0.0, max_it=1)
+    assert info2["residual_first"] <= eps, info2
