@@ -123,6 +123,27 @@ def track_case(q, name, L):
             "fail": st["fail"]}
 
 
+def track_batch_case(q, name, L, B, single):
+    """B copies of the stored path tracked together (one launch per kernel per
+    round): paths per second against the single-path run `single`."""
+    import numpy as np
+
+    from synth.systems import CONFIGS, config_system, start_root
+
+    with open(os.path.join(ROOT, "tests", "golden", f"path_{name}.json")) as fh:
+        fix = json.load(fh)
+    s = config_system(CONFIGS[name])
+    H = q.Homotopy(q.System.from_synth(s), s.gamma)
+    x0 = start_root(np.array(fix["degrees"]), np.array(fix["start_k"]), L)
+    z, st = q.track_paths(H, np.stack([x0] * B), L)
+    same = all(np.array_equal(z[b], z[0]) for b in range(B))
+    secs = st[0]["seconds"]
+    return {"workload": name, "B": B, "seconds": round(secs, 4), "paths_per_s": B / secs,
+            "single_path_seconds": single["seconds"], "speedup_per_path": single["seconds"] * B / secs,
+            "fails": sum(x["fail"] for x in st), "all_endpoints_equal": same,
+            "corrections": st[0]["corrections"], "newton_iterations": st[0]["newton_iterations"]}
+
+
 def quality_report(dd, qd, cpu):
     """Quality up of Section 2 on the n = 64 workload: the same path tracked in
     double double and in quad double on the GPU.  Q = correct decimal places
@@ -313,6 +334,7 @@ def main():
             for name, lim in (("n8_dd", 2), ("n32_dd", 2), ("n64_dd", 2), ("n64_qd", 4)):
                 paths[name] = track_case(q, name, lim)
             out["paths"] = list(paths.values())
+            out["paths_batch"] = [track_batch_case(q, "n64_dd", 2, args.batch, paths["n64_dd"])]
         except Exception as e:  # report, never hide, a failing path
             out["paths"] = [{"error": str(e)}]
     if not args.no_cpu_baseline:

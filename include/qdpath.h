@@ -282,6 +282,17 @@ typedef struct {
 qdp_status qdp_track_path(const qdp_homotopy *h, double *x, qdp_prec prec, const qdp_track_params *p,
                           qdp_track_stats *st, qdp_step_record *step_log, int64_t log_cap, void *hip_stream);
 
+/* Track B paths of one homotopy together (Algorithm 3.1 for each): x [B][n][2][prec]
+ * host memory, in: start solutions, out: end points; stats [B].  Every round
+ * predicts and corrects all unfinished paths with one launch per kernel, each
+ * path at its own t with its own step size, predictor history and Newton loop;
+ * step-size control, stop criterion and end refinement are those of
+ * qdp_track_path, path by path.  Plain control only: predictor SECANT or
+ * QUADRATIC (else QDP_EUNSUPPORTED), no probe mode.  stats[b].seconds is the
+ * time of the whole call.  Calls on one h must not overlap.  1 <= B <= 65536. */
+qdp_status qdp_track_paths(const qdp_homotopy *h, double *x, int32_t B, qdp_prec prec, const qdp_track_params *p,
+                           qdp_track_stats *stats, void *hip_stream);
+
 /* Multiword arithmetic test entry: out[i] = op(a[i], b[i], c[i]) for
  * count elements on the GPU (device pointers, asynchronous).  Real ops take
  * [L] doubles per element, complex ops [2][L].

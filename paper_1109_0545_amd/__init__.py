@@ -33,5 +33,6 @@ from .binding import (  # noqa: F401
     newton_step,
     newton_step_dev,
     track_path,
+    track_paths,
     version,
 )

@@ -145,6 +145,8 @@ SIGNATURES = {
     "qdp_track_params_default": (ct.c_int, [ct.POINTER(TrackParams)]),
     "qdp_track_path": (ct.c_int, [_P, _P, ct.c_int, ct.POINTER(TrackParams), ct.POINTER(TrackStats),
                                   ct.POINTER(StepRecord), ct.c_int64, _P]),
+    "qdp_track_paths": (ct.c_int, [_P, _P, ct.c_int32, ct.c_int, ct.POINTER(TrackParams), ct.POINTER(TrackStats),
+                                   _P]),
     "qdp_arith_batch": (ct.c_int, [ct.c_int32, ct.c_int, ct.c_int64, _P, _P, _P, _P, _P]),
     "qdp_set_timing": (ct.c_int, [ct.c_int32]),
     "qdp_homotopy_last_timing": (ct.c_int, [_P, ct.c_int, _D, _D, ct.POINTER(ct.c_int32), _P]),
@@ -422,6 +424,17 @@ def track_path(h: Homotopy, x0: np.ndarray, prec: int, params: Optional[TrackPar
             d["features"] = np.ctypeslib.as_array(r.features).copy()
             recs.append(d)
     return x, st.as_dict(), recs
+
+
+def track_paths(h: Homotopy, x0: np.ndarray, prec: int, params: Optional[TrackParams] = None, stream=None):
+    """B paths at once: x0 [B][n][2][prec] start solutions.  Returns (end points, list of stats dicts)."""
+    x = np.array(x0, dtype=np.float64, copy=True, order="C")
+    assert x.ndim == 4 and x.shape[1:] == (h.n, 2, prec)
+    nb = x.shape[0]
+    st = (TrackStats * nb)()
+    p = params if params is not None else default_track_params()
+    _check(lib().qdp_track_paths(h.handle, _ptr(x), nb, prec, ct.byref(p), st, _stream(stream)))
+    return x, [st[b].as_dict() for b in range(nb)]
 
 
 def arith_batch(op: str, prec: int, a, b=None, c=None, stream=None):

@@ -21,7 +21,11 @@ hipError_t launch_ge_scaled(int L, int n, int B, double *ab, double *scale, doub
                             hipStream_t s);
 hipError_t launch_arith(int op, int L, int64_t count, const double *a, const double *b, const double *c,
                         double *out, hipStream_t s);
-hipError_t launch_init_state(NewtonState *st, int B, double eps, int max_it, hipStream_t s);
+hipError_t launch_init_state(NewtonState *st, int B, double eps, int max_it, const int *mask, hipStream_t s);
+hipError_t launch_predict_batch(int L, int n, int B, const double *x, const double *xp, const double *xpp,
+                                const double *cf, const int *mask, double *xw, hipStream_t s);
+hipError_t launch_accept_batch(int L, int n, int B, const int *acc, double *x, double *xp, double *xpp,
+                               const double *xw, hipStream_t s);
 hipError_t launch_predict(int L, int n, const double *x, const double *xprev, const double *xprev2, double c1,
                           double c2, double *xpred, double *aux, hipStream_t s);
 hipError_t launch_blend_label(int L, int n, const double *x, const double *xprev, const double *xprev2,
@@ -361,18 +365,22 @@ extern "C" qdp_status qdp_eval_homotopy(const qdp_homotopy *h, double t, const d
 // update).  Every kernel reads the device flag `active` first and returns at
 // once when the loop of Algorithm 4.1 has ended, so the host never waits
 // between iterations.
+// tb (device, nullable): t of each point instead of t; mask (device, nullable):
+// only points with mask[b] != 0 run.
 static qdp_status enqueue_newton(qdp_homotopy *h, Workspace *w, int L, double t, double *x_dev, int B, int mode,
-                                 double eps, int max_it, hipStream_t st) {
+                                 double eps, int max_it, hipStream_t st, const double *tb = nullptr,
+                                 const int *mask = nullptr) {
   const qdp_system *f = h->f;
   const int n = f->n;
-  HIPCHK(qdp::launch_init_state(w->st, B, eps, max_it, st));
+  HIPCHK(qdp::launch_init_state(w->st, B, eps, max_it, mask, st));
   // [A | -h] column-major in limb planes: limb c of (r,k) at c*n(n+1) + k*n + r,
   // one such block per point
   const long ps = (long)n * (n + 1);
   const long pb = ps * 2 * L;
   qdp::EvalOut o{w->ab, ps, 1, n, w->ab + (size_t)n * n, ps, 1, -1.0, w->scale, pb, pb, n};
   const qdp::EvalSplit split{w->part, qdp::kMaxEvalParts};
-  const qdp::HomArgs ha = hom_args(h, L, t, 1);
+  qdp::HomArgs ha = hom_args(h, L, t, 1);
+  ha.tb = tb;
   const bool timing = g_timing != 0;
   if (timing) {
     while (w->ev.size() < 3 * (size_t)max_it) {
@@ -858,6 +866,202 @@ extern "C" qdp_status qdp_track_path(const qdp_homotopy *hc, double *x, qdp_prec
 }
 
 // ------------------------------------------------------------------ arithmetic test entry
+
+// ------------------------------------------------------------------ batched tracker
+
+// Algorithm 3.1 for B paths of one homotopy at once: every round predicts and
+// corrects all unfinished paths with one launch per kernel (each path at its
+// own t with its own step size, predictor history and Newton loop), then
+// applies the plain step-size control path by path on the host.  The end
+// refinement at t = 1 runs the same way.  Plain control only (secant or
+// quadratic predictor).
+extern "C" qdp_status qdp_track_paths(const qdp_homotopy *hc, double *x, int32_t B, qdp_prec prec,
+                                      const qdp_track_params *pp, qdp_track_stats *stats, void *stream) {
+  const int L = (int)prec;
+  if (!hc || !x || !stats) return fail(QDP_EINVAL, "NULL argument");
+  if (B < 1 || B > (1 << 16)) return fail(QDP_EINVAL, "B must be in [1, 65536]");
+  if (!valid_prec(L) || L > hc->f->L) return fail(QDP_EINVAL, "prec must be 1, 2 or 4 and not above the system's");
+  qdp_track_params p;
+  if (pp)
+    p = *pp;
+  else
+    qdp_track_params_default(&p);
+  if (!(p.lambda0 > 0) || !(p.shrink > 0 && p.shrink < 1) || !(p.expand >= 1) || p.max_it_path < 1 ||
+      p.max_it_end < 0 || !(p.lambda_max >= p.lambda0))
+    return fail(QDP_EINVAL, "bad step-size control parameters");
+  if (p.mode != QDP_SOLVE_FULL && p.mode != QDP_SOLVE_MIXED_IR) return fail(QDP_EINVAL, "bad solve mode");
+  if (p.mode == QDP_SOLVE_MIXED_IR && L != 2)
+    return fail(QDP_EUNSUPPORTED, "mixed-precision refinement is implemented for double double");
+  if (p.predictor != QDP_PRED_SECANT && p.predictor != QDP_PRED_QUADRATIC)
+    return fail(QDP_EUNSUPPORTED, "batched tracking uses the secant or the quadratic predictor");
+  if (p.probe) return fail(QDP_EUNSUPPORTED, "probe mode tracks one path");
+  auto *h = const_cast<qdp_homotopy *>(hc);
+  const int n = h->f->n;
+  const size_t per = (size_t)n * 2 * L;
+  qdp_status s = check_point(n * B, L, x);
+  if (s != QDP_OK) return s;
+  std::lock_guard<std::mutex> g(h->mu);
+  Workspace *w = nullptr;
+  if ((s = ensure_ws(h, L, B, &w)) != QDP_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  const auto t_start = std::chrono::steady_clock::now();
+
+  // device: points x, x_prev, x_prev2, working point; coefficients [2][B] and
+  // t [B] in one array; mask and acceptance flags [2][B]
+  double *dx = nullptr, *dxp = nullptr, *dxpp = nullptr, *dxw = nullptr, *dcf = nullptr;
+  int *dflags = nullptr;
+  auto cleanup = [&]() {
+    hipFree(dx);
+    hipFree(dxp);
+    hipFree(dxpp);
+    hipFree(dxw);
+    hipFree(dcf);
+    hipFree(dflags);
+  };
+  hipError_t err = hipMalloc(&dx, per * B * sizeof(double));
+  if (err == hipSuccess) err = hipMalloc(&dxp, per * B * sizeof(double));
+  if (err == hipSuccess) err = hipMalloc(&dxpp, per * B * sizeof(double));
+  if (err == hipSuccess) err = hipMalloc(&dxw, per * B * sizeof(double));
+  if (err == hipSuccess) err = hipMalloc(&dcf, 3 * (size_t)B * sizeof(double));
+  if (err == hipSuccess) err = hipMalloc(&dflags, 2 * (size_t)B * sizeof(int));
+  if (err == hipSuccess) err = hipMemcpyAsync(dx, x, per * B * sizeof(double), hipMemcpyHostToDevice, st);
+  if (err != hipSuccess) {
+    cleanup();
+    return fail(err == hipErrorOutOfMemory ? QDP_ENOMEM : QDP_EDEVICE, hipGetErrorString(err));
+  }
+  int *dmask = dflags, *dacc = dflags + B;
+  double *dtn = dcf + 2 * (size_t)B;
+
+  struct PathState {
+    double t = 0.0, tprev = 0.0, tprev2 = 0.0, lam = 0.0, sum_step = 0.0, min_step = INFINITY, rho = 1.0,
+           prev = INFINITY;
+    int npts = 1, run = 0, end_it = 0;
+    bool done = false, refining = false, end_stop = false;
+    int64_t succ = 0, corr = 0, nit = 0;
+  };
+  std::vector<PathState> ps(B);
+  for (auto &q : ps) q.lam = p.lambda0;
+  std::vector<double> hcf(3 * (size_t)B, 0.0);
+  std::vector<int> hflags(2 * (size_t)B, 0);
+  std::vector<NewtonState> ns(B);
+  const double wq = p.predictor == QDP_PRED_QUADRATIC ? 1.0 : 0.0;
+  const double eps_end = p.eps_end > 0 ? p.eps_end : 64.0 * std::ldexp(1.0, -53 * L);
+  auto run_round = [&](int mode_end) -> qdp_status {
+    // flags and coefficients to the device, predict (path rounds), Newton, states back
+    HIPCHK(hipMemcpyAsync(dcf, hcf.data(), hcf.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(dflags, hflags.data(), hflags.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    qdp_status e;
+    if (!mode_end) {
+      HIPCHK(qdp::launch_predict_batch(L, n, B, dx, dxp, dxpp, dcf, dmask, dxw, st));
+      e = enqueue_newton(h, w, L, 0.0, dxw, B, p.mode, p.eps_path, p.max_it_path, st, dtn, dmask);
+    } else {
+      e = enqueue_newton(h, w, L, 1.0, dx, B, p.mode, 0.0, 1, st, nullptr, dmask);
+    }
+    if (e != QDP_OK) return e;
+    HIPCHK(hipMemcpyAsync(ns.data(), w->st, B * sizeof(NewtonState), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return QDP_OK;
+  };
+  qdp_status rs = QDP_OK;
+  for (;;) {
+    // ---- path rounds
+    int active = 0;
+    for (int b = 0; b < B; ++b) {
+      PathState &q = ps[b];
+      hflags[b] = 0;
+      hflags[B + b] = 0;
+      if (q.done || q.refining) continue;
+      const double step = std::min(q.lam, 1.0 - q.t);
+      const double tn = (q.t + step >= 1.0) ? 1.0 : q.t + step;
+      double c1 = 0.0, c2 = 0.0;
+      if (q.npts >= 2) c1 = -(tn - q.t) / (q.t - q.tprev);
+      if (q.npts >= 3 && wq > 0) {
+        c1 = ((tn - q.t) * (tn - q.tprev2)) / ((q.tprev - q.t) * (q.tprev - q.tprev2));
+        c2 = ((tn - q.t) * (tn - q.tprev)) / ((q.tprev2 - q.t) * (q.tprev2 - q.tprev));
+      }
+      hcf[b] = c1;
+      hcf[B + b] = c2;
+      hcf[2 * (size_t)B + b] = tn;
+      hflags[b] = 1;
+      ++active;
+    }
+    if (active == 0) break;
+    if ((rs = run_round(0)) != QDP_OK) break;
+    for (int b = 0; b < B; ++b) {
+      if (!hflags[b]) continue;
+      PathState &q = ps[b];
+      const double step = std::min(q.lam, 1.0 - q.t);
+      const double tn = hcf[2 * (size_t)B + b];
+      ++q.corr;
+      q.nit += ns[b].iterations;
+      if (ns[b].success) {
+        hflags[B + b] = 1;
+        q.tprev2 = q.tprev;
+        q.tprev = q.t;
+        q.t = tn;
+        q.npts = std::min(q.npts + 1, 3);
+        ++q.succ;
+        q.sum_step += step;
+        q.min_step = std::min(q.min_step, step);
+        if (++q.run >= p.expand_after) {
+          q.lam = std::min(q.lam * p.expand, p.lambda_max);
+          q.run = 0;
+        }
+      } else {
+        q.lam *= p.shrink;
+        q.run = 0;
+      }
+      if (q.t >= 1.0) q.refining = true;
+      else if (q.lam < p.lambda_min || q.corr >= p.max_steps) q.done = true;
+    }
+    HIPCHK(hipMemcpyAsync(dacc, hflags.data() + B, B * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(qdp::launch_accept_batch(L, n, B, dacc, dx, dxp, dxpp, dxw, st));
+  }
+  // ---- end refinement at t = 1: Newton until eps_end, max_it_end, or the
+  // residual stops decreasing, path by path
+  while (rs == QDP_OK) {
+    int active = 0;
+    for (int b = 0; b < B; ++b) {
+      PathState &q = ps[b];
+      hflags[b] = (q.refining && !q.end_stop && q.rho > eps_end && q.end_it < p.max_it_end) ? 1 : 0;
+      active += hflags[b];
+    }
+    if (active == 0) break;
+    if ((rs = run_round(1)) != QDP_OK) break;
+    for (int b = 0; b < B; ++b) {
+      if (!hflags[b]) continue;
+      PathState &q = ps[b];
+      q.rho = ns[b].rho;
+      ++q.end_it;
+      if (ns[b].singular || !(q.rho == q.rho) || q.rho >= q.prev) q.end_stop = true;
+      q.prev = q.rho;
+    }
+  }
+  if (rs == QDP_OK) {
+    err = hipMemcpyAsync(x, dx, per * B * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (err == hipSuccess) err = hipStreamSynchronize(st);
+    if (err != hipSuccess) rs = fail(QDP_EDEVICE, hipGetErrorString(err));
+  }
+  cleanup();
+  if (rs != QDP_OK) return rs;
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  for (int b = 0; b < B; ++b) {
+    const PathState &q = ps[b];
+    qdp_track_stats &o = stats[b];
+    std::memset(&o, 0, sizeof(o));
+    o.fail = q.t < 1.0 ? 1 : 0;
+    o.end_success = (q.refining && q.rho < eps_end) ? 1 : 0;
+    o.t_final = q.t;
+    o.succ_corrections = q.succ;
+    o.corrections = q.corr;
+    o.newton_iterations = q.nit + q.end_it;
+    o.avg_step = q.succ ? q.sum_step / (double)q.succ : 0.0;
+    o.min_step = q.succ ? q.min_step : 0.0;
+    o.seconds = secs;
+    o.end_residual = q.refining ? q.rho : 0.0;
+  }
+  return QDP_OK;
+}
 
 extern "C" qdp_status qdp_arith_batch(int32_t op, qdp_prec prec, int64_t count, const double *a, const double *b,
                                       const double *c, double *out, void *stream) {

@@ -53,7 +53,8 @@ constexpr int kMaxEvalParts = 8;
 struct HomArgs {
   int homotopy;
   double t;
-  double gamma[8];  // [re limbs][im limbs] at the compute L (first 2L used)
+  double gamma[8];     // [re limbs][im limbs] at the compute L (first 2L used)
+  const double *tb;    // [B] t of each point (device), or nullptr: t for every point
 };
 
 // Per-call Newton state kept on the device.

@@ -70,15 +70,16 @@ template <int L>
 __device__ void eval_finish(const EvalArgs<L> &a, int b, int i, int col, C<L> s, double S, const C<L> &pd1,
                             const C<L> &pd) {
   const int n = a.s.n;
+  const double t = a.h.tb ? a.h.tb[b] : a.h.t;
   if (col < n) {
     C<L> Jv = s;
     if (a.h.homotopy) {
-      Jv = cmul_d<L>(s, a.h.t);
+      Jv = cmul_d<L>(s, t);
       if (col == i) {
         const C<L> g = cload<L>(a.h.gamma);
         double e1;
         R<L> omt = rzero<L>();
-        omt.v[0] = two_sum(1.0, -a.h.t, e1);
+        omt.v[0] = two_sum(1.0, -t, e1);
         if (L > 1) omt.v[1] = e1;
         const C<L> w = cmul_r<L>(g, omt);
         const int d = a.s.deg[i];
@@ -92,13 +93,13 @@ __device__ void eval_finish(const EvalArgs<L> &a, int b, int i, int col, C<L> s,
       const C<L> g = cload<L>(a.h.gamma);
       double e1;
       R<L> omt = rzero<L>();
-      omt.v[0] = two_sum(1.0, -a.h.t, e1);
+      omt.v[0] = two_sum(1.0, -t, e1);
       if (L > 1) omt.v[1] = e1;
       const C<L> w = cmul_r<L>(g, omt);
       C<L> gm = pd;
       gm.re = rsub<L>(gm.re, rfrom<L>(1.0));
-      hv = cadd<L>(cmul_d<L>(s, a.h.t), cmul<L>(w, gm));
-      S = fabs(a.h.t) * S + cabs_hi<L>(w) * (cabs_hi<L>(pd) + 1.0);
+      hv = cadd<L>(cmul_d<L>(s, t), cmul<L>(w, gm));
+      S = fabs(t) * S + cabs_hi<L>(w) * (cabs_hi<L>(pd) + 1.0);
     }
     if (a.o.ysign < 0) hv = cneg<L>(hv);
     pstore<L>(a.o.y + (size_t)b * a.o.by + (size_t)i * a.o.sy, a.o.psy, hv);

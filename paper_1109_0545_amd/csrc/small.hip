@@ -9,7 +9,8 @@ using namespace mw;
 
 // Algorithm 4.1 initialises the residual to 1 and loops while it exceeds eps
 // and fewer than Max_It iterations ran.
-__global__ void k_init_state(NewtonState *states, int B, double eps, int max_it) {
+// mask (nullable): points with mask[b] == 0 start inactive (their kernels return at once)
+__global__ void k_init_state(NewtonState *states, int B, double eps, int max_it, const int *mask) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
   NewtonState *s = states + b;
@@ -28,11 +29,11 @@ __global__ void k_init_state(NewtonState *states, int B, double eps, int max_it)
   s->pad = 0;
   s->dz_first = 0.0;
   s->xnorm = 0.0;
-  s->active = (1.0 > eps && max_it > 0) ? 1 : 0;
+  s->active = (1.0 > eps && max_it > 0 && (!mask || mask[b])) ? 1 : 0;
 }
 
-hipError_t launch_init_state(NewtonState *st, int B, double eps, int max_it, hipStream_t s) {
-  hipLaunchKernelGGL(k_init_state, dim3((B + 63) / 64), dim3(64), 0, s, st, B, eps, max_it);
+hipError_t launch_init_state(NewtonState *st, int B, double eps, int max_it, const int *mask, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_state, dim3((B + 63) / 64), dim3(64), 0, s, st, B, eps, max_it, mask);
   return hipGetLastError();
 }
 
@@ -75,6 +76,55 @@ hipError_t launch_predict(int L, int n, const double *x, const double *xprev, co
     case 4: hipLaunchKernelGGL(k_predict<4>, g, b, 0, s, n, x, xprev, xprev2, c1, c2, xpred, aux); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+// Predictor for a batch of paths: point b of xw gets x_b + c1[b] (xp_b - x_b)
+// + c2[b] (xpp_b - x_b) where mask[b] != 0 (see k_predict).  Points are
+// n complex values apart; grid (ceil(n / 64), B).
+template <int L>
+__global__ __launch_bounds__(64) void k_predict_batch(int n, const double *x, const double *xp, const double *xpp,
+                                                      const double *cf, const int *mask, int B, double *xw) {
+  const int b = blockIdx.y, v = blockIdx.x * 64 + threadIdx.x;
+  if (v >= n || !mask[b]) return;
+  const size_t o = ((size_t)b * n + v) * 2 * L;
+  const double c1 = cf[b], c2 = cf[B + b];
+  const C<L> z = cload<L>(x + o);
+  C<L> d = czero<L>();
+  if (c1 != 0.0) d = cmul_d<L>(csub<L>(cload<L>(xp + o), z), c1);
+  if (c2 != 0.0) d = cadd<L>(d, cmul_d<L>(csub<L>(cload<L>(xpp + o), z), c2));
+  cstore<L>(xw + o, cadd<L>(z, d));
+}
+
+hipError_t launch_predict_batch(int L, int n, int B, const double *x, const double *xp, const double *xpp,
+                                const double *cf, const int *mask, double *xw, hipStream_t s) {
+  dim3 g((n + 63) / 64, B), b(64);
+  switch (L) {
+    case 1: hipLaunchKernelGGL(k_predict_batch<1>, g, b, 0, s, n, x, xp, xpp, cf, mask, B, xw); break;
+    case 2: hipLaunchKernelGGL(k_predict_batch<2>, g, b, 0, s, n, x, xp, xpp, cf, mask, B, xw); break;
+    case 4: hipLaunchKernelGGL(k_predict_batch<4>, g, b, 0, s, n, x, xp, xpp, cf, mask, B, xw); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Acceptance for a batch of paths: where acc[b] != 0, (xpp, xp, x) <- (xp, x, xw)
+// for point b (each element read before any write of it).
+__global__ void k_accept_batch(size_t per_point, const int *acc, double *x, double *xp, double *xpp,
+                               const double *xw, size_t count) {
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= count || !acc[q / per_point]) return;
+  const double a = xp[q], c = x[q], w = xw[q];
+  xpp[q] = a;
+  xp[q] = c;
+  x[q] = w;
+}
+
+hipError_t launch_accept_batch(int L, int n, int B, const int *acc, double *x, double *xp, double *xpp,
+                               const double *xw, hipStream_t s) {
+  const size_t per = (size_t)n * 2 * L, count = per * B;
+  hipLaunchKernelGGL(k_accept_batch, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, per, acc, x, xp, xpp,
+                     xw, count);
   return hipGetLastError();
 }
 

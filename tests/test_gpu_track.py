@@ -154,3 +154,49 @@ def test_track_quadratic_predictions_match_oracle():
         same += 1
     say("steps compared", same, "of", len(log), "oracle", len(ref.predictions))
     assert same >= min(30, len(ref.predictions))
+
+
+@pytest.mark.parametrize("name,copies", [("n8_dd", 1), ("n32_dd", 4)])
+def test_track_paths_batch_matches_single_paths(name, copies):
+    """Several paths tracked together (one launch per kernel per round): every
+    path's outcome, counts and end point equal its single-path run, for both
+    predictors (the per-point kernels are the same at these batch sizes); the
+    fixture path reaches z** to double-double accuracy."""
+    import paper_1109_0545_amd as q
+
+    fix = fixture(name)
+    s = config_system(CONFIGS[name])
+    S = q.System.from_synth(s)
+    H = q.Homotopy(S, s.gamma)
+    rng = np.random.Generator(np.random.PCG64(8))
+    ks = [np.array(fix["start_k"])] * copies
+    if copies == 1:  # other start roots: paths that converge elsewhere or fail
+        ks += [rng.integers(0, s.degrees) for _ in range(4)]
+    x0 = np.stack([start_root(s.degrees, k, 2) for k in ks])
+    zss = zss_mpc(fix)
+    for pred in (q.PRED_SECANT, q.PRED_QUADRATIC):
+        p = q.default_track_params(predictor=pred, max_steps=20000)
+        say("track paths", name, "B", len(ks), "predictor", pred)
+        zb, stb = q.track_paths(H, x0, 2, p)
+        singles = {}
+        for b in range(len(ks)):
+            key = tuple(ks[b])
+            if key not in singles:
+                singles[key] = q.track_path(H, x0[b], 2, p)
+            z1, st1, _ = singles[key]
+            for f in ("fail", "succ_corrections", "corrections", "newton_iterations", "end_success"):
+                assert stb[b][f] == st1[f], (b, f, stb[b], st1)
+            assert np.array_equal(zb[b], z1), b
+        assert not stb[0]["fail"] and correct_digits(zb[0], zss) >= 28
+
+
+def test_track_paths_rejects_unsupported_controls():
+    import paper_1109_0545_amd as q
+
+    s = config_system(CONFIGS["n8_dd"])
+    S = q.System.from_synth(s)
+    H = q.Homotopy(S, s.gamma)
+    x0 = start_root(s.degrees, np.zeros(s.n, np.int64), 2)[None]
+    with pytest.raises(q.QdpError) as e:
+        q.track_paths(H, x0, 2, q.default_track_params(probe=1))
+    assert e.value.status == 5
