@@ -20,8 +20,8 @@
 // (interleaved, so that neighbouring lanes read neighbouring table entries).
 // The order used for the prefix/suffix products is lane-major: a lane first
 // forms the suffix products of its own variables, the LM lanes then combine
-// their chunk products with Hillis-Steele scans in both directions (wavefront
-// shuffles), and each lane walks its variables forward once.  A lane keeps
+// their chunk products by a butterfly of wavefront shuffles into the product
+// over the other lanes, and each lane walks its variables forward once.  A lane keeps
 // the running sums of its CH Jacobian entries in registers over all the
 // monomials it visits; the per-polynomial reduction is a fixed-order shuffle
 // butterfly then a fixed-order LDS sum across wavefronts (no atomics: results
@@ -204,8 +204,9 @@ __global__ __launch_bounds__(NT + 64) void k_eval(EvalArgs<L> a) {
   C<L> accv = czero<L>();
   double accS = 0.0;
 
-  auto gval = [&](int v, int e) -> C<L> { return v < n ? pload<L>(Gt + (size_t)e * nv + v, tps) : cone<L>(); };
-  auto qval = [&](int v, int e) -> C<L> { return v < n ? pload<L>(Qt + (size_t)e * nv + v, tps) : czero<L>(); };
+  // table offsets e * nv + v with a 24-bit multiply (e <= 255, nv < 2^16)
+  auto gval = [&](int v, int e) -> C<L> { return v < n ? pload<L>(Gt + __umul24(e, nv) + v, tps) : cone<L>(); };
+  auto qval = [&](int v, int e) -> C<L> { return v < n ? pload<L>(Qt + __umul24(e, nv) + v, tps) : czero<L>(); };
 
   if (pw) {
     if (lane == 0 && a.h.homotopy && a.P == 1) {
@@ -225,34 +226,39 @@ __global__ __launch_bounds__(NT + 64) void k_eval(EvalArgs<L> a) {
     for (int k = 0; k < CH; ++k) ex[k] = er[k * LM];
     const C<L> coef = cload_trunc<L>(a.s.coefs + (size_t)jj * 2 * LS, LS);
 
-    // suffix products of this lane's variables (exclusive), and their product
+    // suffix products of this lane's variables (exclusive; sfx[CH-1] = 1 is
+    // never formed), and the product of all of them
     C<L> sfx[CH];
-    sfx[CH - 1] = cone<L>();
+    C<L> chunk = gval(gl + (CH - 1) * LM, ex[CH - 1]);
+    if constexpr (CH > 1) {
+      sfx[CH - 2] = chunk;
 #pragma unroll
-    for (int k = CH - 2; k >= 0; --k) sfx[k] = cmul<L>(sfx[k + 1], gval(gl + (k + 1) * LM, ex[k + 1]));
-    const C<L> chunk = cmul<L>(sfx[0], gval(gl, ex[0]));
-
-    // inclusive scans of chunk products over the LM lanes of this monomial
-    C<L> fw = chunk, bw = chunk;
-#pragma unroll
-    for (int d = 1; d < LM; d <<= 1) {
-      C<L> y = cshfl_up<L>(fw, d, LM);
-      C<L> z = cshfl_down<L>(bw, d, LM);
-      fw = cselect<L>(gl >= d, cmul<L>(y, fw), fw);
-      bw = cselect<L>(gl + d < LM, cmul<L>(bw, z), bw);
+      for (int k = CH - 3; k >= 0; --k) sfx[k] = cmul<L>(sfx[k + 1], gval(gl + (k + 1) * LM, ex[k + 1]));
+      chunk = cmul<L>(sfx[0], gval(gl, ex[0]));
     }
-    C<L> pre = cshfl_up<L>(fw, 1, LM);
-    C<L> suf = cshfl_down<L>(bw, 1, LM);
-    if (LM == 1 || gl == 0) pre = cone<L>();
-    if (LM == 1 || gl == LM - 1) suf = cone<L>();
+
+    // product of the other LM - 1 lanes' chunk products by a butterfly: after
+    // the exchange at distance d a lane holds the product over its aligned
+    // block of 2d lanes (blk) and that product without its own chunk (others)
+    C<L> run = coef;
+    if constexpr (LM > 1) {
+      C<L> blk = chunk, others = cshfl_xor<L>(chunk, 1, LM);
+      blk = cmul<L>(blk, others);
+#pragma unroll
+      for (int d = 2; d < LM; d <<= 1) {
+        const C<L> p = cshfl_xor<L>(blk, d, LM);
+        others = cmul<L>(others, p);
+        blk = cmul<L>(blk, p);
+      }
+      run = cmul<L>(run, others);
+    }
 
     // walk this lane's variables: run = c * (all factors before v)
-    //                                   * (all factors of later lanes)
-    C<L> run = cmul<L>(cmul<L>(coef, pre), suf);
+    //                                   * (all factors of the other lanes)
 #pragma unroll
     for (int k = 0; k < CH; ++k) {
       const int v = gl + k * LM;
-      C<L> d = cmul<L>(cmul<L>(run, sfx[k]), qval(v, ex[k]));
+      const C<L> d = k < CH - 1 ? cmul<L>(cmul<L>(run, sfx[k]), qval(v, ex[k])) : cmul<L>(run, qval(v, ex[k]));
       if (valid) acc[k] = cadd<L>(acc[k], d);
       run = cmul<L>(run, gval(v, ex[k]));
     }
@@ -370,8 +376,11 @@ hipError_t launch_eval_lm(int LM, const EvalArgs<L> &a, int B, hipStream_t st) {
 
 // Launch for one precision: LM lanes per monomial from CH variables per lane;
 // the split P doubles while fewer than 512 workgroups would run and every
-// part keeps at least one wavefront's worth of monomials; 256 threads when
-// four wavefronts cover a part's monomials in one pass, else 512.
+// part keeps at least one wavefront's worth of monomials.  256 threads on
+// monomials (five wavefronts with the start-power one): with 150-220
+// registers per lane two such workgroups share a compute unit and overlap
+// each other's table and reduction phases, which measured faster than one
+// workgroup of 512 (same at n = 128 double double, 12% at n = 64 quad double).
 template <int L, int CH>
 hipError_t launch_eval_T(const DevSystem &s, const double *x, long bx, int B, const HomArgs &h, const EvalOut &o,
                          const NewtonState *gate, const EvalSplit &sp, hipStream_t st) {
@@ -382,10 +391,7 @@ hipError_t launch_eval_T(const DevSystem &s, const double *x, long bx, int B, co
   if (sp.part)
     while (2 * P <= sp.max_parts && (long)s.n * B * P < 512 && (s.maxm + 2 * P - 1) / (2 * P) >= G) P *= 2;
   EvalArgs<L> a{s, x, bx, h, o, gate, P, sp.part};
-  const int waves = ((s.maxm + P - 1) / P + G - 1) / G;
-  // eight variables per lane need ~220 registers: 256 threads (+ the power wavefront) only
-  hipError_t e = (CH >= 8 && L >= 2) || waves <= 4 ? launch_eval_lm<L, CH, 256>(LM, a, B, st)
-                                                   : launch_eval_lm<L, CH, 512>(LM, a, B, st);
+  hipError_t e = launch_eval_lm<L, CH, 256>(LM, a, B, st);
   if (e != hipSuccess || P == 1) return e;
   hipLaunchKernelGGL(k_eval_sum<L>, dim3(s.n, B), dim3(256), 0, st, a);
   return hipGetLastError();
