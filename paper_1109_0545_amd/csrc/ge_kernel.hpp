@@ -20,8 +20,9 @@
 // global memory.
 // Rows are never swapped: the not-yet-pivoted rows form an ordered list,
 // compacted each step without reordering (double-buffered).  The pivot
-// inverses are kept for the back substitution, which one wavefront runs
-// column by column with register shuffles.
+// inverses are kept for the back substitution: every thread scales the rows
+// of U by them, then one wavefront runs the substitution column by column
+// with lane reads.
 #pragma once
 #include "common.hpp"
 
@@ -310,11 +311,30 @@ __device__ bool eliminate(double *M, size_t PS, int n, const ElimLds<L> &e, bool
   return !singular && steps_done == n;
 }
 
-// Back substitution by wavefront 0 on the eliminated matrix: returns through
-// the limb planes of `out` (n elements, plane stride n) the solution of the
-// upper triangle (rows perm[0..n-1]) with right-hand side rhs_of(i) for the
-// pivot-ordered index i.  Lane l keeps entries l + 64u in registers; each
-// column's solution value travels by lane reads, not LDS.
+// Rows of U scaled by their pivot inverses: U(i, k) / U(i, i) for i < k < n
+// in place (the right-hand-side column n is left as it is), by every thread
+// of the workgroup, one column per group of lanes (consecutive lanes take
+// consecutive pivot rows of one column).  Takes the product by the pivot
+// inverse out of the back substitution's column-to-column chain.
+template <int L, int NT>
+__device__ void scale_upper(double *M, size_t PS, int n, const int *perm, const C<L> *invp) {
+  for (int q = threadIdx.x; q < n * n; q += NT) {
+    const int k = q / n, i = q - k * n;
+    if (i < k) {
+      double *p = M + (size_t)k * n + perm[i];
+      pstore<L>(p, PS, cmul<L>(pload<L>(p, PS), invp[i]));
+    }
+  }
+}
+
+// Back substitution by wavefront 0 on the eliminated matrix whose U rows were
+// scaled by scale_upper: returns through the limb planes of `out` (n
+// elements, plane stride n) the solution of the upper triangle (rows
+// perm[0..n-1]) with right-hand side rhs_of(i) for the pivot-ordered index i.
+// With y_i = rhs_i / U(i, i) and U' the scaled rows, x_j = y_j - sum_{k > j}
+// U'(j, k) x_k: lane l keeps y_l, y_{l+64}, ... in registers, and once x_j is
+// final (column j's turn) it travels by lane reads to every lane, which
+// subtracts U'(i, j) x_j from its rows i < j.
 template <int L, typename Rhs, int RPL = kRowsPerLane>
 __device__ void back_substitute(const double *M, size_t PS, int n, const int *perm, const C<L> *invp, double *out,
                                 Rhs rhs_of) {
@@ -328,7 +348,7 @@ __device__ void back_substitute(const double *M, size_t PS, int n, const int *pe
     b[u] = czero<L>();
     pr[u] = 0;
     if (i < n) {
-      b[u] = rhs_of(i);
+      b[u] = cmul<L>(rhs_of(i), invp[i]);
       pr[u] = perm[i];
     }
   }
@@ -336,13 +356,12 @@ __device__ void back_substitute(const double *M, size_t PS, int n, const int *pe
     C<L> bj = czero<L>();
 #pragma unroll
     for (int u = 0; u < RPL; ++u) bj = cselect<L>(lane + 64 * u == j, b[u], bj);
-    const C<L> dj = cmul<L>(cbcast<L>(bj, j & 63), invp[j]);
+    const C<L> xj = cbcast<L>(bj, j & 63);
 #pragma unroll
     for (int u = 0; u < RPL; ++u) {
-      if (64 * u > j) break;  // wave-uniform: no row of this slot is at or above j
+      if (64 * u >= j) break;  // wave-uniform: no row of this slot is above j
       const int i = lane + 64 * u;
-      if (i < j) b[u] = cfms<L>(b[u], pload<L>(at(pr[u], j), PS), dj);
-      else if (i == j) b[u] = dj;
+      if (i < j) b[u] = cfms<L>(b[u], pload<L>(at(pr[u], j), PS), xj);
     }
   }
 #pragma unroll
@@ -427,6 +446,8 @@ __global__ __launch_bounds__(NT) void k_ge(GeArgs<L> a) {
   const double rho = residual_of<L, NT>(M + (size_t)n * n, PS, n, scale, redbuf, bad);
   double pmax = 0.0, pmin = __builtin_inf();
   const bool ok = eliminate<L, NT, RPL>(M, PS, n, el, bad, pmax, pmin);
+  if (ok) scale_upper<L, NT>(M, PS, n, el.perm, el.invp);  // ok is the same in every thread
+  __syncthreads();
   auto rhs = [&](int i) { return pload<L>(M + (size_t)n * n + el.perm[i], PS); };
   if (ok && wave == 0) back_substitute<L, decltype(rhs), RPL>(M, PS, n, el.perm, el.invp, bb, rhs);
   __syncthreads();

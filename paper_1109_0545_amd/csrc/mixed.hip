@@ -82,6 +82,8 @@ __global__ __launch_bounds__(NT) void k_mixed(MixedArgs a) {
 
   double pmax = 0.0, pmin = __builtin_inf();
   const bool ok = eliminate<1, NT>(M64, PS, n, el, bad, pmax, pmin);
+  if (ok) scale_upper<1, NT>(M64, PS, n, el.perm, el.invp);  // U rows / pivots; the multipliers stay
+  __syncthreads();
 
   // ---- first correction from the eliminated right-hand side
   if (ok && wave == 0)
