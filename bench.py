@@ -250,6 +250,9 @@ def main():
     ap.add_argument("--batch", type=int, default=256, help="points per launch of the batched comparison line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 256 MiB device copy (for HBM counter calibration)")
+    ap.add_argument("--profile-batch", action="store_true",
+                    help="run only the batched Newton line (n=64 double double, --batch points per launch, "
+                         "--steps iterations) and print its rates (for profiling the batched evaluation)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -272,6 +275,10 @@ def main():
     L = 2
     t = 0.5
     mode = q.SOLVE_FULL if args.mode == "full" else q.SOLVE_MIXED_IR
+    if args.profile_batch:
+        r = newton_rate(q, "n64_dd", L, mode, args.steps, args.warmup, t, B=args.batch)
+        print(json.dumps(rate_entry("n64_dd", L, args.batch, mode, *r[:5])))
+        return
     rate, ms, ev_us, ge_us, sysm, info = newton_rate(q, "n64_dd", L, mode, args.steps, args.warmup, t)
 
     n = sysm.n
