@@ -123,6 +123,53 @@ def track_case(q, name, L):
             "fail": st["fail"]}
 
 
+def common_support_case(q, steps: int = 1000, warmup: int = 20):
+    """The shape of the paper's Table 1 (1,000 Newton iterations on a 40 x 40
+    system whose polynomials share one support of 200 monomials, average
+    degree 40): the seeded stand-in c40_dd, complex double double, t = 1 (the
+    target system) from 1e-6 off its planted root, convergence exit off."""
+    import numpy as np
+    import torch
+
+    from synth.systems import CONFIGS, config_system
+
+    sysm = config_system(CONFIGS["c40_dd"])
+    S = q.System.from_synth(sysm)
+    H = q.Homotopy(S, sysm.gamma)
+    rng = np.random.default_rng(0)
+    x0 = sysm.zstar.copy()
+    x0[:, :, 0] += 1e-6 * rng.standard_normal((sysm.n, 2))
+    x0[:, :, 1] = 0.0
+    x = torch.from_numpy(x0[None].copy()).cuda()
+    stream = torch.cuda.current_stream()
+    q.newton_batch_dev(H, 1.0, x, 1, 2, 0, eps=0.0, max_it=warmup, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    q.newton_batch_dev(H, 1.0, x, 1, 2, 0, eps=0.0, max_it=steps, stream=stream)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    info = q.last_info_batch(H, 2, 1, stream=stream)[0]
+    q.binding.set_timing(True)
+    q.newton_batch_dev(H, 1.0, x, 1, 2, 0, eps=0.0, max_it=min(steps, 500), stream=stream)
+    torch.cuda.synchronize()
+    q.binding.set_timing(False)
+    eval_ms, solve_ms, launches = q.binding.last_timing(H, 2, stream=stream)
+    n, M = sysm.n, int(sysm.poly_offsets[1])
+    cm, ca = eval_ops(sysm.exps[:M], np.array([0, M]))  # the support's partials, once
+    ev_flops = cm * CMUL + ca * CADD + n * (n + 1) * M * CFMA  # + the coefficient product
+    ev_us = eval_ms / launches * 1e3
+    return {"workload": "c40_dd: 40 x 40, common support of 200 monomials, exponents in {0,1,2} (average "
+                        "degree 40), seed 4; complex double double, t = 1, from 1e-6 off the planted root",
+            "newton_iterations": steps, "seconds": el, "steps_per_s": steps / el,
+            "residual_last": info["residual_last"], "singular": info["singular"],
+            "eval_us": ev_us, "solve_us": solve_ms / launches * 1e3,
+            "eval_flops": ev_flops, "eval_frac_fp64_peak": ev_flops / ev_us / 1e6 / FP64_PEAK_TFLOPS,
+            "paper_table1_seconds": {"1 thread": 40.778, "8 threads": 6.177,
+                                     "context": "two quad-core 3.2 GHz Xeons, the paper's earlier evaluation "
+                                                "scheme, precision not stated; their system and generator "
+                                                "are not published"}}
+
+
 def track_batch_case(q, name, L, B, single):
     """B copies of the stored path tracked together (one launch per kernel per
     round): paths per second against the single-path run `single`."""
@@ -335,6 +382,7 @@ def main():
             extra.append(ent)
         # B points per launch: independent paths at one t (the rate summed over points)
         out["solve_modes"] = extra
+        out["common_support"] = common_support_case(q)
     paths = {}
     if not args.no_paths:
         try:

@@ -66,6 +66,13 @@ typedef struct qdp_homotopy qdp_homotopy;
  *   coefs        : [terms][2][prec] doubles
  *   prec         : limbs stored; the system can later be evaluated at this or
  *                  any lower precision (limbs are truncated), never higher
+ * Common support (the workload of Table 1): when n >= 2 and every polynomial
+ * has exactly f_0's exponent rows in the same order, every evaluation of the
+ * system forms the partials and values of those M monomials once per point and
+ * multiplies by the n x M coefficient matrix (a dense complex product); the
+ * results are those of the sparse evaluation up to rounding order.  The
+ * system then holds a scratch for one point: evaluation calls on one such
+ * system (qdp_eval_jacobian*, qdp_eval_homotopy*) must not overlap.
  * Errors: QDP_EINVAL (sizes, offsets, a polynomial without terms, the power
  * table n*(max exponent+1) beyond the LDS budget), QDP_ENONFINITE (a
  * coefficient limb), QDP_ENOMEM / QDP_EDEVICE. */

@@ -69,11 +69,13 @@ static bool valid_prec(int p) { return p == 1 || p == 2 || p == 4; }
 struct qdp_system {
   int n = 0, L = 0, terms = 0, emax = 0, maxm = 0, npad = 0;
   std::vector<int32_t> deg;
+  int supp = 0;  // common support: M monomials shared by every polynomial (0: not common)
   int32_t *d_offsets = nullptr, *d_deg = nullptr;
   uint8_t *d_exps = nullptr;
   double *d_coefs = nullptr;
+  double *d_suppv = nullptr;  // common support: monomial partials of one point (eval entry points)
   DevSystem dev() const {
-    return DevSystem{n, terms, L, npad, emax, maxm, d_offsets, d_exps, d_coefs, d_deg};
+    return DevSystem{n, terms, L, npad, emax, maxm, d_offsets, d_exps, d_coefs, d_deg, supp};
   }
 };
 
@@ -83,6 +85,7 @@ struct Workspace {
   double *ab = nullptr;     // [bcap] (n+1) x n column-major [A | -h]
   double *scale = nullptr;  // [bcap][n]
   double *part = nullptr;   // split-evaluation partial rows (EvalSplit)
+  double *suppv = nullptr;  // [bcap] common-support monomial partials (EvalSplit)
   double *x = nullptr;      // [n] point (compute precision)
   double *xprev = nullptr;  // [n] previous accepted point
   double *xprev2 = nullptr; // [n] the accepted point before that
@@ -110,9 +113,10 @@ static void free_batch(Workspace &w) {
   hipFree(w.ab);
   hipFree(w.scale);
   hipFree(w.part);
+  hipFree(w.suppv);
   hipFree(w.lu);
   hipFree(w.st);
-  w.ab = w.scale = w.part = w.lu = nullptr;
+  w.ab = w.scale = w.part = w.suppv = w.lu = nullptr;
   w.st = nullptr;
   w.bcap = 0;
 }
@@ -145,6 +149,7 @@ static qdp_status ensure_ws(qdp_homotopy *h, int L, int B, Workspace **out) {
     HIPCHK(hipMalloc(&w.st, Bs * sizeof(NewtonState)));
     const size_t pd = qdp::eval_part_doubles(L, n, B);
     if (pd > 0) HIPCHK(hipMalloc(&w.part, pd * sizeof(double)));
+    if (h->f->supp > 0) HIPCHK(hipMalloc(&w.suppv, Bs * qdp::eval_supp_doubles(L, n, h->f->supp) * sizeof(double)));
     if (L == 2) HIPCHK(hipMalloc(&w.lu, Bs * n * (n + 1) * 2 * sizeof(double)));
     w.bcap = B;
   }
@@ -214,6 +219,20 @@ extern "C" qdp_status qdp_system_create(int32_t n, const int32_t *off, const uin
       s->deg[i] = std::max(s->deg[i], tot);
     }
   s->emax = emax;
+  // common support (n >= 2): every polynomial has f_0's exponent rows, in
+  // the same order; then the monomial partials are formed once per point
+  {
+    const int M = off[1];
+    bool common = n >= 2;
+    for (int i = 1; i < n && common; ++i) {
+      if (off[i + 1] - off[i] != M) {
+        common = false;
+        break;
+      }
+      common = std::memcmp(exps + (size_t)off[i] * n, exps, (size_t)M * n) == 0;
+    }
+    s->supp = common ? M : 0;
+  }
   // the power tables of the evaluation kernel live in LDS; the reduction
   // area reuses the same space
   if (table_bytes(n, emax, L) > 150 * 1024) {
@@ -225,6 +244,8 @@ extern "C" qdp_status qdp_system_create(int32_t n, const int32_t *off, const uin
   if (e == hipSuccess) e = hipMalloc(&s->d_deg, n * sizeof(int32_t));
   if (e == hipSuccess) e = hipMalloc(&s->d_exps, padded.size());
   if (e == hipSuccess) e = hipMalloc(&s->d_coefs, (size_t)terms * 2 * L * sizeof(double));
+  if (e == hipSuccess && s->supp > 0)
+    e = hipMalloc(&s->d_suppv, qdp::eval_supp_doubles(L, n, s->supp) * sizeof(double));
   if (e == hipSuccess) e = hipMemcpy(s->d_offsets, off, (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(s->d_deg, s->deg.data(), n * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(s->d_exps, padded.data(), padded.size(), hipMemcpyHostToDevice);
@@ -244,6 +265,7 @@ extern "C" void qdp_system_destroy(qdp_system *s) {
   hipFree(s->d_deg);
   hipFree(s->d_exps);
   hipFree(s->d_coefs);
+  hipFree(s->d_suppv);
   delete s;
 }
 
@@ -294,7 +316,8 @@ static qdp_status eval_common(const qdp_system *f, const qdp_homotopy *h, double
   // row-major [i][v][2][L] and [i][2][L]: limb c at offset c
   const long e = 2 * L;
   qdp::EvalOut o{jac_dev, 1, (long)f->n * e, e, y_dev, 1, e, 1.0, scale_dev, 0, 0, 0};
-  const qdp::EvalSplit whole{nullptr, 1};  // one workgroup per polynomial: no scratch
+  // one workgroup per polynomial: no split scratch; a common-support system uses its own scratch
+  const qdp::EvalSplit whole{nullptr, 1, f->d_suppv, 1};
   HIPCHK(qdp::launch_eval(L, f->dev(), x_dev, 0, 1, hom_args(h, L, t, h != nullptr), o, nullptr, whole, st));
   return QDP_OK;
 }
@@ -378,7 +401,7 @@ static qdp_status enqueue_newton(qdp_homotopy *h, Workspace *w, int L, double t,
   const long ps = (long)n * (n + 1);
   const long pb = ps * 2 * L;
   qdp::EvalOut o{w->ab, ps, 1, n, w->ab + (size_t)n * n, ps, 1, -1.0, w->scale, pb, pb, n};
-  const qdp::EvalSplit split{w->part, qdp::kMaxEvalParts};
+  const qdp::EvalSplit split{w->part, qdp::kMaxEvalParts, w->suppv, w->bcap};
   qdp::HomArgs ha = hom_args(h, L, t, 1);
   ha.tb = tb;
   const bool timing = g_timing != 0;
@@ -469,7 +492,7 @@ extern "C" qdp_status qdp_eval_homotopy_batch_dev(const qdp_homotopy *hc, double
   const int n = h->f->n;
   const long e = 2 * L;
   qdp::EvalOut o{jac, 1, (long)n * e, e, y, 1, e, 1.0, scale, (long)n * n * e, (long)n * e, n};
-  const qdp::EvalSplit split{w->part, qdp::kMaxEvalParts};
+  const qdp::EvalSplit split{w->part, qdp::kMaxEvalParts, w->suppv, w->bcap};
   HIPCHK(qdp::launch_eval(L, h->f->dev(), x, (long)n * e, B, hom_args(h, L, t, 1), o, nullptr, split,
                           (hipStream_t)stream));
   return QDP_OK;

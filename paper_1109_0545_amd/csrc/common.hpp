@@ -22,6 +22,8 @@ struct DevSystem {
   const uint8_t *exps;     // [terms][npad], zero padded
   const double *coefs;     // [terms][2][LS]
   const int32_t *deg;      // [n] total degree d_i of f_i
+  int supp;                // common support: every polynomial has the same M = supp exponent
+                           // rows (those of f_0); 0 otherwise
 };
 
 // Where evaluation results go.  All strides count doubles.  Limb c of the
@@ -46,6 +48,8 @@ struct EvalOut {
 struct EvalSplit {
   double *part;
   int max_parts;
+  double *supp_v;  // common-support systems: scratch for the monomial partials of
+  int supp_cap;    // up to supp_cap points (eval_supp_doubles each); required there
 };
 constexpr int kMaxEvalParts = 8;
 
@@ -84,5 +88,14 @@ hipError_t launch_eval(int L, const DevSystem &s, const double *x, long bx, int 
                        const EvalOut &o, const NewtonState *gate, const EvalSplit &split, hipStream_t st);
 // Doubles of partial-row scratch a split evaluation of B points needs.
 size_t eval_part_doubles(int L, int n, int B);
+// Doubles of monomial-partial scratch per point of a common-support system:
+// V [M][2L limb planes][n+1] (the partials and value of every support
+// monomial), then the start-system powers x_i^(d_i - 1), x_i^(d_i) of every
+// row ([n][2][2L]).
+__host__ __device__ inline size_t supp_pow_offset(int M, int n, int L) { return (size_t)M * 2 * L * (n + 1); }
+__host__ __device__ inline size_t supp_v_doubles(int M, int n, int L) {
+  return supp_pow_offset(M, n, L) + (size_t)n * 4 * L;
+}
+size_t eval_supp_doubles(int L, int n, int supp);
 
 }  // namespace qdp

@@ -19,8 +19,13 @@ size_t eval_part_doubles(int L, int n, int B) {
 }
 
 
+size_t eval_supp_doubles(int L, int n, int supp) { return supp_v_doubles(supp, n, L); }
+
 hipError_t launch_eval(int L, const DevSystem &s, const double *x, long bx, int B, const HomArgs &h,
                        const EvalOut &o, const NewtonState *gate, const EvalSplit &split, hipStream_t st) {
+  // a common-support system is evaluated through its monomial partials: the
+  // caller must bring the scratch for them
+  if (s.supp > 0 && (!split.supp_v || B > split.supp_cap)) return hipErrorInvalidValue;
   switch (L) {
     case 1: return launch_eval_f64(s, x, bx, B, h, o, gate, split, st);
     case 2: return launch_eval_dd(s, x, bx, B, h, o, gate, split, st);

@@ -6,6 +6,7 @@ namespace qdp {
 
 hipError_t launch_eval_f64(const DevSystem &s, const double *x, long bx, int B, const HomArgs &h, const EvalOut &o,
                          const NewtonState *gate, const EvalSplit &sp, hipStream_t st) {
+  if (s.supp > 0) return launch_supp_T<1, 8>(s, x, bx, B, h, o, gate, sp.supp_v, st);
   return launch_eval_T<1, 8>(s, x, bx, B, h, o, gate, sp, st);
 }
 

@@ -151,6 +151,73 @@ __global__ __launch_bounds__(256) void k_eval_sum(EvalArgs<L> a) {
 // consecutive variables read consecutive banks whatever their exponents
 __host__ __device__ inline int table_stride(int n) { return (n + 31) & ~31; }
 
+// Power tables of one point in LDS, by threads tid = start, start + step, ...:
+// Gt[e][v] = x_v^e and Qt[e][v] = e x_v^(e-1) for e <= E1 - 1 (limb planes
+// tps apart, rows nv apart).  The derivative table folds the common factor
+// x^(a-1) of Section 6 into a lookup.
+template <int L>
+__device__ void power_tables(const double *x, int n, int E1, int nv, size_t tps, double *Gt, double *Qt, int start,
+                             int step) {
+  for (int v = start; v < n; v += step) {
+    const C<L> xv = cload<L>(x + (size_t)v * 2 * L);
+    C<L> p = cone<L>();
+    pstore<L>(Gt + v, tps, p);
+    pstore<L>(Qt + v, tps, czero<L>());
+    for (int e = 1; e < E1; ++e) {
+      pstore<L>(Qt + (size_t)e * nv + v, tps, cmul_d<L>(p, (double)e));
+      p = cmul<L>(p, xv);
+      pstore<L>(Gt + (size_t)e * nv + v, tps, p);
+    }
+  }
+}
+
+// Speelpenning's products for one monomial c x^a spread over LM lanes of a
+// wavefront, lane gl owning the variables gl + k LM (k < CH, exponents ex[k]):
+// emit(k, d) receives d = c * (partial of x^a with respect to that variable)
+// for each of the lane's variables; the return value is c x^a (in every lane
+// of the group).  gval(v, e) / qval(v, e) read x_v^e and e x_v^(e-1) (one and
+// zero past the last variable).  UNIT: c = 1, its product is not formed.
+//
+// Each lane forms the suffix products of its own variables (the last one is
+// one and is not formed); the LM lanes combine their chunk products by a
+// butterfly of xor shuffles: after the exchange at distance d a lane holds
+// the product over its aligned block of 2d lanes (blk) and that product
+// without its own chunk (others); the lane then walks its variables forward
+// from c * others.  Four complex products per variable, as in Section 6.
+template <int L, int CH, int LM, bool UNIT, class GV, class QV, class Emit>
+__device__ __forceinline__ C<L> monomial_walk(const int (&ex)[CH], const C<L> &coef, int gl, GV gval, QV qval,
+                                              Emit emit) {
+  C<L> sfx[CH];
+  C<L> chunk = gval(gl + (CH - 1) * LM, ex[CH - 1]);
+  if constexpr (CH > 1) {
+    sfx[CH - 2] = chunk;
+#pragma unroll
+    for (int k = CH - 3; k >= 0; --k) sfx[k] = cmul<L>(sfx[k + 1], gval(gl + (k + 1) * LM, ex[k + 1]));
+    chunk = cmul<L>(sfx[0], gval(gl, ex[0]));
+  }
+  C<L> run = UNIT ? cone<L>() : coef;
+  if constexpr (LM > 1) {
+    C<L> blk = chunk, others = cshfl_xor<L>(chunk, 1, LM);
+    blk = cmul<L>(blk, others);
+#pragma unroll
+    for (int d = 2; d < LM; d <<= 1) {
+      const C<L> p = cshfl_xor<L>(blk, d, LM);
+      others = cmul<L>(others, p);
+      blk = cmul<L>(blk, p);
+    }
+    run = UNIT ? others : cmul<L>(run, others);
+  }
+  // run = c * (all factors before v) * (all factors of the other lanes)
+#pragma unroll
+  for (int k = 0; k < CH; ++k) {
+    const int v = gl + k * LM;
+    const C<L> d = k < CH - 1 ? cmul<L>(cmul<L>(run, sfx[k]), qval(v, ex[k])) : cmul<L>(run, qval(v, ex[k]));
+    emit(k, d);
+    run = cmul<L>(run, gval(v, ex[k]));
+  }
+  return run;
+}
+
 // NT threads work on monomials; with one part per polynomial (P = 1) the
 // launch adds a wavefront that forms the start-system powers meanwhile (a
 // chain of dependent products that would otherwise sit in the tail of the
@@ -226,6 +293,8 @@ __global__ __launch_bounds__(NT + 64) void k_eval(EvalArgs<L> a) {
     for (int k = 0; k < CH; ++k) ex[k] = er[k * LM];
     const C<L> coef = cload_trunc<L>(a.s.coefs + (size_t)jj * 2 * LS, LS);
 
+    // the walk of monomial_walk written out here: through the shared function
+    // the compiler scheduled this kernel 3-10% slower (measured)
     // suffix products of this lane's variables (exclusive; sfx[CH-1] = 1 is
     // never formed), and the product of all of them
     C<L> sfx[CH];
@@ -394,6 +463,178 @@ hipError_t launch_eval_T(const DevSystem &s, const double *x, long bx, int B, co
   hipError_t e = launch_eval_lm<L, CH, 256>(LM, a, B, st);
   if (e != hipSuccess || P == 1) return e;
   hipLaunchKernelGGL(k_eval_sum<L>, dim3(s.n, B), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- common support
+// Systems whose polynomials all sum the same M monomials with their own
+// coefficients, f_i = sum_m C[i][m] x^(a_m) (the common-support workload of
+// the paper's Table 1).  The monomials' partials and values V[m][k] (k < n:
+// partial with respect to x_k; k = n: the value) are formed once per point
+// by Speelpenning's products (k_supp_v), and the evaluation is the dense
+// complex product Y[i][k] = sum_m C[i][m] V[m][k] (k_supp_gemm), blended and
+// stored exactly like the sparse evaluation.  The support is the exponent
+// rows [0, M) (those of f_0; every polynomial has the same rows).
+
+
+template <int L> struct SuppArgs {
+  DevSystem s;  // s.supp = M
+  const double *x;
+  long bx;
+  HomArgs h;
+  EvalOut o;
+  const NewtonState *gate;
+  double *V;  // [B] points of supp_v_doubles each: V, then the start-system powers
+};
+
+// one group of LM lanes per support monomial; blockIdx.y = point.  The last
+// workgroup of a point forms the start-system powers of every row instead
+// (one chain per thread), stored after V for the product kernel.
+template <int L, int CH, int LM, int NT>
+__global__ __launch_bounds__(NT) void k_supp_v(SuppArgs<L> a) {
+  constexpr int G = 64 / LM, W = NT / 64, SLOTS = W * G;
+  const int b = blockIdx.y;
+  if (a.gate && !a.gate[b].active) return;
+  const double *x = a.x + (size_t)b * a.bx;
+  extern __shared__ double smem[];
+  const int n = a.s.n, M = a.s.supp;
+  if (blockIdx.x == gridDim.x - 1) {
+    double *P = a.V + (size_t)b * supp_v_doubles(M, n, L) + supp_pow_offset(M, n, L);
+    if (a.h.homotopy)
+      for (int i = threadIdx.x; i < n; i += NT) {
+        C<L> q1, q;
+        start_powers<L>(x + (size_t)i * 2 * L, a.s.deg[i], q1, q);
+        cstore<L>(P + (size_t)i * 4 * L, q1);
+        cstore<L>(P + (size_t)i * 4 * L + 2 * L, q);
+      }
+    return;
+  }
+  const int E1 = a.s.emax + 1;
+  const int nv = table_stride(n);
+  const size_t tps = (size_t)E1 * nv;
+  double *Gt = smem, *Qt = smem + 2 * L * tps;
+  const int tid = threadIdx.x;
+  power_tables<L>(x, n, E1, nv, tps, Gt, Qt, tid, NT);
+  __syncthreads();
+  const int lane = tid & 63, wave = tid >> 6, grp = lane / LM, gl = lane % LM;
+  const int m = blockIdx.x * SLOTS + wave * G + grp;
+  if (m >= M) return;  // whole groups leave together: the shuffles stay inside a group
+  auto gval = [&](int v, int e) -> C<L> { return v < n ? pload<L>(Gt + __umul24(e, nv) + v, tps) : cone<L>(); };
+  auto qval = [&](int v, int e) -> C<L> { return v < n ? pload<L>(Qt + __umul24(e, nv) + v, tps) : czero<L>(); };
+  const uint8_t *er = a.s.exps + (size_t)m * a.s.npad + gl;
+  int ex[CH];
+#pragma unroll
+  for (int k = 0; k < CH; ++k) ex[k] = er[k * LM];
+  double *Vm = a.V + (size_t)b * supp_v_doubles(M, n, L) + (size_t)m * 2 * L * (n + 1);
+  const size_t vps = (size_t)n + 1;
+  const C<L> val = monomial_walk<L, CH, LM, true>(ex, cone<L>(), gl, gval, qval, [&](int k, const C<L> &d) {
+    const int v = gl + k * LM;
+    if (v < n) pstore<L>(Vm + v, vps, d);
+  });
+  if (gl == 0) pstore<L>(Vm + n, vps, val);
+}
+
+constexpr int kSuppCols = 16;   // output columns per workgroup
+constexpr int kSuppParts = 32;  // monomial parts per column, added by a fixed tree
+
+// blockIdx = (row i, column block, point); thread (part p, column k): the
+// part's sum over m of C[i][m] V[m][k], then the parts by a fixed pairwise
+// tree, the blend and the store
+template <int L>
+__global__ __launch_bounds__(kSuppCols * kSuppParts) void k_supp_gemm(SuppArgs<L> a) {
+  const int i = blockIdx.x, b = blockIdx.z;
+  if (a.gate && !a.gate[b].active) return;
+  const int n = a.s.n, M = a.s.supp, LS = a.s.LS;
+  const int kl = threadIdx.x % kSuppCols, p = threadIdx.x / kSuppCols;
+  const int k = blockIdx.y * kSuppCols + kl;
+  constexpr int RP = kSuppCols * kSuppParts;  // plane stride of the part sums
+  __shared__ double red[2 * L * RP];
+  __shared__ double redS[kSuppParts];
+  const int chunk = (M + kSuppParts - 1) / kSuppParts;
+  const int m0 = min(M, p * chunk), m1 = min(M, m0 + chunk);
+  C<L> acc = czero<L>();
+  double S = 0.0;
+  if (k <= n) {
+    const double *V = a.V + (size_t)b * supp_v_doubles(M, n, L) + k;
+    const double *Ci = a.s.coefs + (size_t)a.s.offsets[i] * 2 * LS;
+    const size_t vps = (size_t)n + 1, vm = 2 * (size_t)L * vps;
+    // U monomials' loads issued together (the sum is a dependent chain; the
+    // loads are not), then their terms added in order
+    constexpr int U = L >= 4 ? 4 : 8;
+    for (int m = m0; m < m1; m += U) {
+      C<L> cb[U], vb[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int mm = m + u < m1 ? m + u : m1 - 1;  // a valid address; its term is not added
+        cb[u] = cload_trunc<L>(Ci + (size_t)mm * 2 * LS, LS);
+        vb[u] = pload<L>(V + (size_t)mm * vm, vps);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (m + u < m1) {
+          acc = cfms<L>(acc, cneg<L>(cb[u]), vb[u]);  // acc + c v
+          if (k == n) S += cabs_hi<L>(cb[u]) * cabs_hi<L>(vb[u]);
+        }
+    }
+  }
+  pstore<L>(red + p * kSuppCols + kl, RP, acc);
+  if (k == n) redS[p] = S;
+#pragma unroll
+  for (int w = kSuppParts / 2; w >= 1; w >>= 1) {
+    __syncthreads();
+    if (p < w) {
+      const C<L> o = pload<L>(red + (p + w) * kSuppCols + kl, RP);
+      acc = cadd<L>(acc, o);
+      pstore<L>(red + p * kSuppCols + kl, RP, acc);
+    }
+  }
+  if (p != 0 || k > n) return;
+  double SS = 0.0;
+  if (k == n)
+    for (int q = 0; q < kSuppParts; ++q) SS += redS[q];
+  C<L> pd1 = czero<L>(), pd = cone<L>();
+  if (a.h.homotopy) {
+    const double *P = a.V + (size_t)b * supp_v_doubles(M, n, L) + supp_pow_offset(M, n, L) + (size_t)i * 4 * L;
+    pd1 = cload<L>(P);
+    pd = cload<L>(P + 2 * L);
+  }
+  const C<L> sum = acc;
+  const EvalArgs<L> ea{a.s, a.x, a.bx, a.h, a.o, a.gate, 1, nullptr};
+  eval_finish<L>(ea, b, i, k, sum, SS, pd1, pd);
+}
+
+// Common-support evaluation of B points: V and the start powers into the
+// caller's scratch (B * supp_v_doubles), then the product.
+template <int L, int CH>
+hipError_t launch_supp_T(const DevSystem &s, const double *x, long bx, int B, const HomArgs &h, const EvalOut &o,
+                         const NewtonState *gate, double *V, hipStream_t st) {
+  const int LM = next_pow2((s.n + CH - 1) / CH);
+  if (LM > 64 || B < 1 || s.supp < 1 || !V) return hipErrorInvalidValue;
+  constexpr int NT = 128;
+  SuppArgs<L> a{s, x, bx, h, o, gate, V};
+  const int slots = (NT / 64) * (64 / LM);
+  const dim3 grid((s.supp + slots - 1) / slots + 1, B);  // + the start-power workgroup
+  const size_t nv = ((size_t)s.n + 31) & ~(size_t)31;
+  const size_t lds = 2 * 2 * (size_t)L * (s.emax + 1) * nv * sizeof(double);
+  switch (LM) {
+#define QDP_SV(X)                                                                                       \
+  case X:                                                                                               \
+    if (lds > 64 * 1024) {                                                                              \
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_supp_v<L, CH, X, NT>),        \
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);         \
+      if (e != hipSuccess) return e;                                                                    \
+    }                                                                                                   \
+    hipLaunchKernelGGL((k_supp_v<L, CH, X, NT>), grid, dim3(NT), lds, st, a);                           \
+    break;
+    QDP_SV(1) QDP_SV(2) QDP_SV(4) QDP_SV(8) QDP_SV(16) QDP_SV(32) QDP_SV(64)
+#undef QDP_SV
+    default:
+      return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const dim3 g2(s.n, (s.n + 1 + kSuppCols - 1) / kSuppCols, B);
+  hipLaunchKernelGGL(k_supp_gemm<L>, g2, dim3(kSuppCols * kSuppParts), 0, st, a);
   return hipGetLastError();
 }
 

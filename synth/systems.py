@@ -24,6 +24,12 @@ used is not published):
 Random draws use ``numpy.random.Generator(PCG64(seed))`` in a fixed order:
 exponents ``[n][m][n]``, coefficient angles ``[n][m]``, the angle of gamma,
 root phases ``[n]``, then redraws of duplicate exponent rows.
+
+Common-support workloads (the system of the paper's Table 1: 40 polynomials
+in 40 variables sharing one support of 200 monomials, average degree 40 and
+at most 80, i.e. exponents uniform in {0,1,2}): one support ``[m][n]`` is
+drawn in place of ``[n][m][n]`` and every polynomial uses its rows in the
+same order; the other draws and the planting are as above.
 """
 
 from __future__ import annotations
@@ -76,6 +82,7 @@ class Config:
     E: int
     L: int
     seed: int
+    common: bool = False  # every polynomial has the same m exponent rows
 
 
 CONFIGS: Dict[str, Config] = {
@@ -84,6 +91,8 @@ CONFIGS: Dict[str, Config] = {
     "n64_qd": Config("n64_qd", 64, 64, 4, 4, 2),
     "n64_dd": Config("n64_dd", 64, 64, 4, 2, 2),  # same draws as n64_qd, DD limbs
     "n128_dd": Config("n128_dd", 128, 128, 3, 2, 3),
+    # the paper's Table 1 shape: common support of 200 monomials, degree 40 on average
+    "c40_dd": Config("c40_dd", 40, 200, 2, 2, 4, common=True),
 }
 
 
@@ -140,15 +149,22 @@ def _dedupe(rng, exps: np.ndarray, E: int) -> None:
 
 
 def make_system(
-    n: int, m: int, E: int, L: int, seed: int, plant: bool = True
+    n: int, m: int, E: int, L: int, seed: int, plant: bool = True, common: bool = False
 ) -> System:
     """Draw one random system (see module docstring for the recipe)."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    exps = rng.integers(0, E + 1, size=(n, m, n), dtype=np.int64)
+    if common:
+        support = rng.integers(0, E + 1, size=(1, m, n), dtype=np.int64)
+    else:
+        exps = rng.integers(0, E + 1, size=(n, m, n), dtype=np.int64)
     theta_c = rng.random((n, m))
     theta_g = rng.random()
     phase = rng.integers(0, 2**PHASE_BITS, size=n, dtype=np.int64)
-    _dedupe(rng, exps, E)
+    if common:
+        _dedupe(rng, support, E)
+        exps = np.repeat(support, n, axis=0)
+    else:
+        _dedupe(rng, exps, E)
 
     coefs = np.zeros((n * m, 2, L))
     with mpmath.workprec(_PREC_BITS):
@@ -182,7 +198,7 @@ def make_system(
 
 
 def config_system(cfg: Config, plant: bool = True) -> System:
-    return make_system(cfg.n, cfg.m, cfg.E, cfg.L, cfg.seed, plant=plant)
+    return make_system(cfg.n, cfg.m, cfg.E, cfg.L, cfg.seed, plant=plant, common=cfg.common)
 
 
 def start_root(degrees: np.ndarray, k: np.ndarray, L: int) -> np.ndarray:

@@ -172,6 +172,29 @@ def test_singular_jacobian_is_reported():
     assert np.array_equal(xg, x)
 
 
+@pytest.mark.parametrize("name, prec, mode",
+                         [("n8_dd", 2, 0), ("n32_dd", 2, 0), ("n32_dd", 2, 1), ("n64_qd", 4, 0), ("n128_dd", 2, 0)])
+def test_singular_later_column_is_reported(name, prec, mode):
+    # t = 0: J = diag(gamma d_i x_i^(d_i - 1)); with one coordinate x_k = 0
+    # (d_k >= 2) and the others on the unit circle, column k is the first
+    # column without a nonzero pivot, found by the look-ahead step of column
+    # k - 1 (middle and last column)
+    import paper_1109_0545_amd as q
+
+    s = config_system(CONFIGS[name])
+    S = q.System.from_synth(s)
+    H = q.Homotopy(S, s.gamma)
+    cand = [k for k in range(s.n) if s.degrees[k] >= 2]
+    for k in sorted({cand[len(cand) // 2], cand[-1]}):
+        x = np.zeros((s.n, 2, prec))
+        x[:, 0, 0] = 1.0
+        x[k, 0, 0] = 0.0
+        say(f"newton singular column {k} {name} mode {mode}")
+        xg, info = q.newton_step(H, 0.0, x, prec, mode=mode, eps=1e-10, max_it=4)
+        assert info["singular"] == 1 and not info["success"] and info["iterations"] == 1, (k, info)
+        assert np.array_equal(xg, x)
+
+
 def test_residual_sequence_matches_oracle():
     # four single iterations from a perturbed planted root at t = 1: every
     # residual agrees with the oracle's Newton run (quadratic convergence in
