@@ -170,6 +170,87 @@ def common_support_case(q, steps: int = 1000, warmup: int = 20):
                                                 "are not published"}}
 
 
+def cu_study(q, B: int = 256, q_dd: int = 30, q_qd: int = 63):
+    """Speedup and quality up with p compute units (Section 2's notions, p =
+    CUs instead of cores): Newton iterations of B points of the n=64 path (the
+    batched line) in double double and quad double on a stream restricted to
+    p CUs (hipExtStreamCreateWithCUMask; the runtime accepts masks of at least
+    8 CUs, one per XCD, so p = 8 .. all).  speedup(p) = T(8) / T(p), and the
+    single-CU time is estimated as 8 T(8) (optimal speedup below 8 CUs, the
+    paper's own assumption for its cores).  Quality up at fixed time T_DD(1):
+    p* = the CUs with T_QD(p*) = T_DD(1) (log-interpolated between measured p,
+    optimal speedup below 8), and the paper's linear estimate y(p) = 1 +
+    (Q_QD/Q_DD - 1)(p - 1)/(p* - 1), capped at Q_QD/Q_DD; q_dd, q_qd are the
+    correct decimal places of the n=64 path endpoint in each precision."""
+    import ctypes as ct
+    import math
+
+    import numpy as np
+    import torch
+
+    from synth.systems import CONFIGS, config_system
+
+    q.binding.lib()
+    hip_path = next((ln.split()[-1] for ln in open("/proc/self/maps") if "libamdhip64" in ln), None)
+    if hip_path is None:
+        raise RuntimeError("HIP runtime not mapped")
+    hip = ct.CDLL(hip_path)  # the runtime copy the library and torch already use
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    ps = [p for p in (8, 16, 32, 64, 128, 256) if p < ncu] + [ncu]
+    with open(os.path.join(ROOT, "tests", "golden", "path_n64_dd.json")) as fh:
+        fix = json.load(fh)
+    times = {}
+    for L, K, name in ((2, 2, "n64_dd"), (4, 1, "n64_qd")):
+        s_l = config_system(CONFIGS[name])
+        H = q.Homotopy(q.System.from_synth(s_l), s_l.gamma)
+        p0 = path_point(fix, L)
+        x0 = torch.from_numpy(np.stack([p0 * (1.0 + 1e-6 * b) for b in range(B)])).cuda()
+        q.newton_batch_dev(H, 0.5, x0.clone(), B, L, 0, eps=0.0, max_it=1)  # workspace, code load
+        torch.cuda.synchronize()
+        for p in ps:
+            mask = (ct.c_uint32 * ((ncu + 31) // 32))()
+            for c in range(p):
+                mask[c // 32] |= 1 << (c % 32)
+            st = ct.c_void_p()
+            rc = hip.hipExtStreamCreateWithCUMask(ct.byref(st), len(mask), mask)
+            if rc != 0:
+                raise RuntimeError(f"hipExtStreamCreateWithCUMask({p} CUs) returned {rc}")
+            x = x0.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            q.newton_batch_dev(H, 0.5, x, B, L, 0, eps=0.0, max_it=K, stream=st.value)
+            rc = hip.hipStreamSynchronize(st)
+            times[(L, p)] = (time.perf_counter() - t0) / K
+            hip.hipStreamDestroy(st)
+            if rc != 0:
+                raise RuntimeError(f"hipStreamSynchronize returned {rc}")
+    p0 = ps[0]
+    rows = [{"cus": p, "dd_s_per_iteration": times[(2, p)], "qd_s_per_iteration": times[(4, p)],
+             "dd_speedup_vs_8": times[(2, p0)] / times[(2, p)], "qd_speedup_vs_8": times[(4, p0)] / times[(4, p)]}
+            for p in ps]
+    t_dd1 = p0 * times[(2, p0)]  # single-CU estimate
+    if times[(4, p0)] <= t_dd1:
+        pstar = p0 * times[(4, p0)] / t_dd1
+    else:
+        pstar = None
+        for a, b in zip(ps, ps[1:]):
+            if times[(4, a)] > t_dd1 >= times[(4, b)]:
+                la, lb = math.log(times[(4, a)]), math.log(times[(4, b)])
+                f = (la - math.log(t_dd1)) / (la - lb)
+                pstar = math.exp(math.log(a) + f * (math.log(b) - math.log(a)))
+    cap = q_qd / q_dd
+
+    def y(p):
+        if pstar is None:
+            return None
+        return cap if pstar <= 1.0 else min(cap, 1 + (cap - 1) * (p - 1) / (pstar - 1))
+
+    return {"workload": f"n=64 (seed 2), {B} points of the path at t = 0.5 per launch, full elimination; "
+                        "seconds per Newton iteration on a stream masked to p CUs",
+            "rows": rows, "dd_single_cu_estimate_s": t_dd1, "Q_dd": q_dd, "Q_qd": q_qd,
+            "p_star_cus": pstar, "quality_up_8_cus": y(8), "quality_up_all_cus": y(ncu)}
+
+
 def track_batch_case(q, name, L, B, single):
     """B copies of the stored path tracked together (one launch per kernel per
     round): paths per second against the single-path run `single`."""
@@ -297,6 +378,8 @@ def main():
     ap.add_argument("--batch", type=int, default=256, help="points per launch of the batched comparison line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 256 MiB device copy (for HBM counter calibration)")
+    ap.add_argument("--cu-study", action="store_true",
+                    help="run only the speedup / quality-up study over compute units and print it")
     ap.add_argument("--profile-batch", action="store_true",
                     help="run only the batched Newton line (n=64 double double, --batch points per launch, "
                          "--steps iterations) and print its rates (for profiling the batched evaluation)")
@@ -322,6 +405,9 @@ def main():
     L = 2
     t = 0.5
     mode = q.SOLVE_FULL if args.mode == "full" else q.SOLVE_MIXED_IR
+    if args.cu_study:
+        print(json.dumps(cu_study(q, B=args.batch)))
+        return
     if args.profile_batch:
         r = newton_rate(q, "n64_dd", L, mode, args.steps, args.warmup, t, B=args.batch)
         print(json.dumps(rate_entry("n64_dd", L, args.batch, mode, *r[:5])))
@@ -400,6 +486,12 @@ def main():
         out["cpu_baseline"] = cpu_baseline(config_system(cfg), path_point(fix, L), t)
     if "n64_dd" in paths and "n64_qd" in paths:
         out["quality_up"] = quality_report(paths["n64_dd"], paths["n64_qd"], out.get("cpu_baseline"))
+    if not args.no_extra:
+        qu = out.get("quality_up") or {}
+        try:
+            out["cu_study"] = cu_study(q, B=args.batch, q_dd=qu.get("Q_dd", 30), q_qd=qu.get("Q_qd", 63))
+        except Exception as e:  # report, never hide
+            out["cu_study"] = {"error": str(e)}
     print(json.dumps(out))
 
 
