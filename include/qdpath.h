@@ -66,8 +66,9 @@ typedef struct qdp_homotopy qdp_homotopy;
  *   coefs        : [terms][2][prec] doubles
  *   prec         : limbs stored; the system can later be evaluated at this or
  *                  any lower precision (limbs are truncated), never higher
- * Common support (the workload of Table 1): when n >= 2 and every polynomial
- * has exactly f_0's exponent rows in the same order, every evaluation of the
+ * Common support (the workload of Table 1): when n >= 2, every polynomial
+ * has exactly f_0's exponent rows in the same order and the M monomials'
+ * partials of one point take at most 8 MiB (M (n+1) 2 prec doubles), every evaluation of the
  * system forms the partials and values of those M monomials once per point and
  * multiplies by the n x M coefficient matrix (a dense complex product); the
  * results are those of the sparse evaluation up to rounding order.  The

@@ -231,6 +231,9 @@ extern "C" qdp_status qdp_system_create(int32_t n, const int32_t *off, const uin
       }
       common = std::memcmp(exps + (size_t)off[i] * n, exps, (size_t)M * n) == 0;
     }
+    // and only while the partials of one point stay modest (the scratch is
+    // per point: a batch of B points holds B of them)
+    if (common && qdp::supp_v_doubles(M, n, L) * sizeof(double) > (size_t(8) << 20)) common = false;
     s->supp = common ? M : 0;
   }
   // the power tables of the evaluation kernel live in LDS; the reduction

@@ -155,3 +155,54 @@ def test_common_newton_converges_to_planted_root():
     assert info["success"] and not info["singular"] and info["iterations"] <= 6, info
     err = np.abs((xg[:, :, 0] - s.zstar[:, :, 0]) + (xg[:, :, 1] - s.zstar[:, :, 1])).max()
     assert err <= 1e-25, err
+
+
+def dense_quadratic_common(n=3, seed=19):
+    """n polynomials sharing the dense support of all monomials of degree <= 2
+    (random unit-circle coefficients): the total-degree homotopy's 2^n paths all
+    end at the 2^n (generically finite, distinct) roots."""
+    import itertools
+
+    rows = [e for e in itertools.product(range(3), repeat=n) if sum(e) <= 2]
+    m = len(rows)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    exps = np.array(rows * n, dtype=np.uint8)
+    ang = rng.random(n * m) * 2 * np.pi
+    coefs = np.zeros((n * m, 2, 2))
+    coefs[:, 0, 0], coefs[:, 1, 0] = np.cos(ang), np.sin(ang)
+    g = rng.random() * 2 * np.pi
+    gamma = np.array([[np.cos(g), 0.0], [np.sin(g), 0.0]])
+    return System(n, 2, (np.arange(n + 1) * m).astype(np.int32), exps, coefs, gamma,
+                  np.zeros((n, 2, 2)), np.zeros(n, np.int64), np.full(n, 2, np.int32))
+
+
+def test_common_track_paths_match_single_paths_and_end_at_roots():
+    # Algorithm 3.1 on a common-support system: the batched tracker gives
+    # every path exactly its single-path run, every path reaches t = 1 at a
+    # root of f (scaled residual at the double-double level, evaluated by the
+    # oracle at the end point), and the 2^n roots are distinct
+    import itertools
+
+    import paper_1109_0545_amd as q
+    from oracle.evaluate import residual
+    from synth.systems import start_root
+
+    s = dense_quadratic_common()
+    H = q.Homotopy(q.System.from_synth(s), s.gamma)
+    ks = [np.array(k, np.int64) for k in itertools.product(range(2), repeat=s.n)]
+    x0 = np.stack([start_root(s.degrees, k, 2) for k in ks])
+    p = q.default_track_params(predictor=q.PRED_QUADRATIC, max_steps=20000)
+    say("common track paths B", len(ks))
+    zb, stb = q.track_paths(H, x0, 2, p)
+    for b in range(len(ks)):
+        z1, st1, _ = q.track_path(H, x0[b], 2, p)
+        for f in ("fail", "succ_corrections", "corrections", "newton_iterations", "end_success"):
+            assert stb[b][f] == st1[f], (b, f, stb[b], st1)
+        assert np.array_equal(zb[b], z1), b
+        assert not stb[b]["fail"] and stb[b]["end_success"], (b, stb[b])
+        res = o_eval_system(s.exps, s.coefs, s.poly_offsets, zb[b])
+        assert residual(res) <= 1e-26, (b, residual(res))
+    ends = zb[:, :, :, 0]  # leading limbs
+    for a in range(len(ks)):
+        for b in range(a):
+            assert np.abs(ends[a] - ends[b]).max() > 1e-6, (a, b)
