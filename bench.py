@@ -453,6 +453,9 @@ def main():
             "traffic": measured_traffic("traffic_k_ge_n64_dd.json") if dom.startswith("elimination") else None,
             "algorithmic_flops_per_launch": dom_flops,
             "avg_launch_us": dom_us,
+            # one path's elimination is one workgroup, i.e. one of the 256 CUs:
+            # its rate against that CU's share of the FP64 peak
+            "frac_of_one_cu": achieved / (FP64_PEAK_TFLOPS / 256),
         },
         "kernels": {"eval_us": ev_us, "solve_us": ge_us, "eval_flops": ev_flops, "solve_flops": ge_flops},
     }

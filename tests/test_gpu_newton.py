@@ -65,6 +65,38 @@ def test_one_step_n64_qd():
     one_step_parity("n64_qd", 4, form="quotient")
 
 
+def test_one_step_n64_dd():
+    one_step_parity("n64_dd", 2, form="quotient")
+
+
+@pytest.mark.parametrize("n", [48, 57, 64])
+def test_elimination_sizes_and_batch(n):
+    # sizes up to the largest matrix kept in LDS (odd and even n): a batch of
+    # points, the first against the oracle, each bit for bit equal to its
+    # single-point call
+    import torch
+
+    import paper_1109_0545_amd as q
+    from synth.systems import make_system, random_point
+
+    s = make_system(n, 12, 2, 2, 40 + n)
+    S = q.System.from_synth(s)
+    H = q.Homotopy(S, s.gamma)
+    B, t = 3, 0.4
+    xs = np.stack([random_point(n, 2, seed=60 + b, spread=0.05) for b in range(B)])
+    say("elimination n", n, "B", B)
+    stream = torch.cuda.current_stream()
+    xd = torch.from_numpy(xs).cuda()
+    q.newton_batch_dev(H, t, xd, B, 2, eps=0.0, max_it=1, stream=stream)
+    infos = q.last_info_batch(H, 2, B, stream=stream)
+    xg = xd.cpu().numpy()
+    for b in range(B):
+        x1, info1 = q.newton_step(H, t, xs[b], 2, eps=0.0, max_it=1)
+        assert np.array_equal(xg[b], x1), b
+        if b == 0:
+            check_step(s, xs[b], t, 2, xg[b], infos[b], "quotient")
+
+
 @pytest.mark.parametrize("name", ["n8_dd", "n32_dd"])
 def test_one_step_mixed_precision(name):
     # FP64 factorization + double-double refinement: same bound as the full
@@ -158,11 +190,12 @@ def test_loop_semantics_on_gpu():
     assert info["iterations"] == 0 and not info["success"]
 
 
-def test_singular_jacobian_is_reported():
+@pytest.mark.parametrize("name", ["n8_dd", "n64_dd"])
+def test_singular_jacobian_is_reported(name):
     # t = 0: h = gamma (x^d - 1); at x = 0 the Jacobian gamma d x^(d-1) vanishes
     import paper_1109_0545_amd as q
 
-    s = config_system(CONFIGS["n8_dd"])
+    s = config_system(CONFIGS[name])
     S = q.System.from_synth(s)
     H = q.Homotopy(S, s.gamma)
     x = np.zeros((s.n, 2, 2))
@@ -173,19 +206,20 @@ def test_singular_jacobian_is_reported():
 
 
 @pytest.mark.parametrize("name, prec, mode",
-                         [("n8_dd", 2, 0), ("n32_dd", 2, 0), ("n32_dd", 2, 1), ("n64_qd", 4, 0), ("n128_dd", 2, 0)])
+                         [("n8_dd", 2, 0), ("n32_dd", 2, 0), ("n32_dd", 2, 1), ("n64_qd", 4, 0), ("n64_dd", 2, 0),
+                          ("n128_dd", 2, 0)])
 def test_singular_later_column_is_reported(name, prec, mode):
     # t = 0: J = diag(gamma d_i x_i^(d_i - 1)); with one coordinate x_k = 0
     # (d_k >= 2) and the others on the unit circle, column k is the first
     # column without a nonzero pivot, found by the look-ahead step of column
-    # k - 1 (middle and last column)
+    # k - 1 (a quarter in, the middle and the last column)
     import paper_1109_0545_amd as q
 
     s = config_system(CONFIGS[name])
     S = q.System.from_synth(s)
     H = q.Homotopy(S, s.gamma)
     cand = [k for k in range(s.n) if s.degrees[k] >= 2]
-    for k in sorted({cand[len(cand) // 2], cand[-1]}):
+    for k in sorted({cand[len(cand) // 4], cand[len(cand) // 2], cand[-1]}):
         x = np.zeros((s.n, 2, prec))
         x[:, 0, 0] = 1.0
         x[k, 0, 0] = 0.0
