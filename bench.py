@@ -380,6 +380,8 @@ def main():
                     help="run only a plain 256 MiB device copy (for HBM counter calibration)")
     ap.add_argument("--cu-study", action="store_true",
                     help="run only the speedup / quality-up study over compute units and print it")
+    ap.add_argument("--profile-common", action="store_true",
+                    help="run only the common-support line (--steps Newton iterations) and print it")
     ap.add_argument("--profile-batch", action="store_true",
                     help="run only the batched Newton line (n=64 double double, --batch points per launch, "
                          "--steps iterations) and print its rates (for profiling the batched evaluation)")
@@ -407,6 +409,9 @@ def main():
     mode = q.SOLVE_FULL if args.mode == "full" else q.SOLVE_MIXED_IR
     if args.cu_study:
         print(json.dumps(cu_study(q, B=args.batch)))
+        return
+    if args.profile_common:
+        print(json.dumps(common_support_case(q, steps=args.steps)))
         return
     if args.profile_batch:
         r = newton_rate(q, "n64_dd", L, mode, args.steps, args.warmup, t, B=args.batch)
