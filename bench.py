@@ -170,6 +170,22 @@ def common_support_case(q, steps: int = 1000, warmup: int = 20):
                                                 "are not published"}}
 
 
+def equal_time_units(t_lo_1: float, t_hi_p: float, p: float) -> float:
+    """Section 2: the units (cores, here CUs) that bring a run taking t_hi_p on
+    p units down to t_lo_1, under optimal speedup: (t_hi_p / t_lo_1) p."""
+    return t_hi_p / t_lo_1 * p
+
+
+def quality_up_linear(p: int, p_star: float, ratio: float) -> float:
+    """Section 2's quality-up estimate at p units: y(1) = 1 and y = ratio
+    (Q_hi / Q_lo) at p* rounded up to whole units, linear in between (capped
+    at ratio beyond)."""
+    pc = math.ceil(p_star - 1e-9)
+    if pc <= 1:
+        return ratio
+    return min(ratio, 1 + (ratio - 1) * (p - 1) / (pc - 1))
+
+
 def cu_study(q, B: int = 256, q_dd: int = 30, q_qd: int = 63):
     """Speedup and quality up with p compute units (Section 2's notions, p =
     CUs instead of cores): Newton iterations of B points of the n=64 path (the
@@ -180,8 +196,8 @@ def cu_study(q, B: int = 256, q_dd: int = 30, q_qd: int = 63):
     paper's own assumption for its cores).  Quality up at fixed time T_DD(1):
     p* = the CUs with T_QD(p*) = T_DD(1) (log-interpolated between measured p,
     optimal speedup below 8), and the paper's linear estimate y(p) = 1 +
-    (Q_QD/Q_DD - 1)(p - 1)/(p* - 1), capped at Q_QD/Q_DD; q_dd, q_qd are the
-    correct decimal places of the n=64 path endpoint in each precision."""
+    (Q_QD/Q_DD - 1)(p - 1)/(ceil(p*) - 1), capped at Q_QD/Q_DD; q_dd, q_qd are
+    the correct decimal places of the n=64 path endpoint in each precision."""
     import ctypes as ct
     import math
 
@@ -230,7 +246,7 @@ def cu_study(q, B: int = 256, q_dd: int = 30, q_qd: int = 63):
             for p in ps]
     t_dd1 = p0 * times[(2, p0)]  # single-CU estimate
     if times[(4, p0)] <= t_dd1:
-        pstar = p0 * times[(4, p0)] / t_dd1
+        pstar = equal_time_units(t_dd1, times[(4, p0)], p0)
     else:
         pstar = None
         for a, b in zip(ps, ps[1:]):
@@ -241,9 +257,7 @@ def cu_study(q, B: int = 256, q_dd: int = 30, q_qd: int = 63):
     cap = q_qd / q_dd
 
     def y(p):
-        if pstar is None:
-            return None
-        return cap if pstar <= 1.0 else min(cap, 1 + (cap - 1) * (p - 1) / (pstar - 1))
+        return None if pstar is None else quality_up_linear(p, pstar, cap)
 
     return {"workload": f"n=64 (seed 2), {B} points of the path at t = 0.5 per launch, full elimination; "
                         "seconds per Newton iteration on a stream masked to p CUs",
