@@ -218,10 +218,13 @@ __device__ __forceinline__ C<L> monomial_walk(const int (&ex)[CH], const C<L> &c
   return run;
 }
 
-// NT threads work on monomials; with one part per polynomial (P = 1) the
-// launch adds a wavefront that forms the start-system powers meanwhile (a
-// chain of dependent products that would otherwise sit in the tail of the
-// workgroup); split evaluations form them in k_eval_sum.
+// NT threads work on monomials.  With one part per polynomial (P = 1, the
+// batched case) thread 0 forms the start-system powers in the workgroup's
+// tail: a chain of dependent products that the other workgroups sharing the
+// compute unit cover (an extra wavefront for it cost a workgroup slot per CU:
+// measured 33% slower at 256 points); split evaluations form them in
+// k_eval_sum.  The register budget is that of NT + 64 threads (five
+// wavefronts), which keeps three four-wavefront workgroups per CU.
 template <int L, int CH, int LM, int NT>
 __global__ __launch_bounds__(NT + 64) void k_eval(EvalArgs<L> a) {
   constexpr int G = 64 / LM;  // monomials per wavefront at a time
@@ -239,11 +242,10 @@ __global__ __launch_bounds__(NT + 64) void k_eval(EvalArgs<L> a) {
   double *Gt = smem;                   // x_v^e          plane c at Gt + c*tps + e*nv + v
   double *Qt = smem + 2 * L * tps;     // e x_v^(e-1)
   const int tid = threadIdx.x;
-  const bool pw = tid >= NT;  // the start-power wavefront
   __shared__ double powbuf[4 * L];
 
   // ---- power tables
-  for (int v = tid; v < n && !pw; v += NT) {
+  for (int v = tid; v < n; v += NT) {
     const C<L> xv = cload<L>(x + (size_t)v * 2 * L);
     C<L> p = cone<L>();
     pstore<L>(Gt + v, tps, p);
@@ -275,15 +277,7 @@ __global__ __launch_bounds__(NT + 64) void k_eval(EvalArgs<L> a) {
   auto gval = [&](int v, int e) -> C<L> { return v < n ? pload<L>(Gt + __umul24(e, nv) + v, tps) : cone<L>(); };
   auto qval = [&](int v, int e) -> C<L> { return v < n ? pload<L>(Qt + __umul24(e, nv) + v, tps) : czero<L>(); };
 
-  if (pw) {
-    if (lane == 0 && a.h.homotopy && a.P == 1) {
-      C<L> pd1, pd;
-      start_powers<L>(x + (size_t)i * 2 * L, a.s.deg[i], pd1, pd);
-      cstore<L>(powbuf, pd1);
-      cstore<L>(powbuf + 2 * L, pd);
-    }
-  }
-  for (int base = t0; base < t1 && !pw; base += SLOTS) {
+  for (int base = t0; base < t1; base += SLOTS) {
     const int j = base + slot;
     const bool valid = j < t1;
     const int jj = valid ? j : t0;
@@ -340,7 +334,7 @@ __global__ __launch_bounds__(NT + 64) void k_eval(EvalArgs<L> a) {
 
   // ---- reduction over the monomial groups of a wavefront (fixed butterfly)
 #pragma unroll
-  for (int off = LM; off < 64 && !pw; off <<= 1) {
+  for (int off = LM; off < 64; off <<= 1) {
 #pragma unroll
     for (int k = 0; k < CH; ++k) acc[k] = cadd<L>(acc[k], cshfl_xor<L>(acc[k], off, 64));
     accv = cadd<L>(accv, cshfl_xor<L>(accv, off, 64));
@@ -351,7 +345,7 @@ __global__ __launch_bounds__(NT + 64) void k_eval(EvalArgs<L> a) {
   const size_t rps = (size_t)W * rn;  // plane size of the reduction buffer [W][n+1]
   double *red = smem;
   double *redS = smem + 2 * L * rps;
-  if (lane < LM && !pw) {
+  if (lane < LM) {
 #pragma unroll
     for (int k = 0; k < CH; ++k) {
       const int v = gl + k * LM;
@@ -366,8 +360,14 @@ __global__ __launch_bounds__(NT + 64) void k_eval(EvalArgs<L> a) {
 
   // ---- fixed-order sum over wavefronts; one part: blend and store; several
   // parts: store this part's row for k_eval_sum
-  if (pw) return;
   if (a.P == 1) {
+    if (tid == 0 && a.h.homotopy) {
+      C<L> q1, q;
+      start_powers<L>(x + (size_t)i * 2 * L, a.s.deg[i], q1, q);
+      cstore<L>(powbuf, q1);
+      cstore<L>(powbuf + 2 * L, q);
+    }
+    __syncthreads();  // a.P is the same in every thread
     C<L> pd1 = czero<L>(), pd = cone<L>();
     if (a.h.homotopy) {
       pd1 = cload<L>(powbuf);
@@ -416,8 +416,7 @@ inline int next_pow2(int v) {
 
 template <int L, int CH, int NT>
 hipError_t launch_eval_lm(int LM, const EvalArgs<L> &a, int B, hipStream_t st) {
-  // the start-power wavefront only when one workgroup finishes its row
-  dim3 grid(a.s.n * a.P, B), block(a.P == 1 && a.h.homotopy ? NT + 64 : NT);
+  dim3 grid(a.s.n * a.P, B), block(NT);
   const size_t lds = eval_lds_bytes_nt(L, a.s, NT);
   if (lds > 64 * 1024) {
     hipError_t e = hipSuccess;
@@ -445,11 +444,11 @@ hipError_t launch_eval_lm(int LM, const EvalArgs<L> &a, int B, hipStream_t st) {
 
 // Launch for one precision: LM lanes per monomial from CH variables per lane;
 // the split P doubles while fewer than 512 workgroups would run and every
-// part keeps at least one wavefront's worth of monomials.  256 threads on
-// monomials (five wavefronts with the start-power one): with 150-220
-// registers per lane two such workgroups share a compute unit and overlap
-// each other's table and reduction phases, which measured faster than one
-// workgroup of 512 (same at n = 128 double double, 12% at n = 64 quad double).
+// part keeps at least one wavefront's worth of monomials.  256 threads: with
+// 150-250 registers per lane several such workgroups share a compute unit
+// and overlap each other's table and reduction phases, which measured faster
+// than 512 threads (same at n = 128 double double, 12% at n = 64 quad double)
+// and than 128 (20-40%).
 template <int L, int CH>
 hipError_t launch_eval_T(const DevSystem &s, const double *x, long bx, int B, const HomArgs &h, const EvalOut &o,
                          const NewtonState *gate, const EvalSplit &sp, hipStream_t st) {
