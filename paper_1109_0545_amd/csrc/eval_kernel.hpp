@@ -459,7 +459,12 @@ hipError_t launch_eval_T(const DevSystem &s, const double *x, long bx, int B, co
   if (sp.part)
     while (2 * P <= sp.max_parts && (long)s.n * B * P < 512 && (s.maxm + 2 * P - 1) / (2 * P) >= G) P *= 2;
   EvalArgs<L> a{s, x, bx, h, o, gate, P, sp.part};
-  hipError_t e = launch_eval_lm<L, CH, 256>(LM, a, B, st);
+  // a split part with at most half of a 256-thread workgroup's monomial
+  // slots (one path at n <= 64 in double double) runs on 128 threads: no
+  // idle wavefronts in the walk, half the reduction (measured 3% faster)
+  const int per_part = (s.maxm + P - 1) / P;
+  hipError_t e = (P > 1 && L == 2 && CH == 4 && per_part <= 2 * G) ? launch_eval_lm<L, CH, 128>(LM, a, B, st)
+                                                                    : launch_eval_lm<L, CH, 256>(LM, a, B, st);
   if (e != hipSuccess || P == 1) return e;
   hipLaunchKernelGGL(k_eval_sum<L>, dim3(s.n, B), dim3(256), 0, st, a);
   return hipGetLastError();
