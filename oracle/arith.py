@@ -15,7 +15,7 @@ of u_L = 2^(-53L) times a componentwise scale:
 * complex div/inv:   |a/b| (modulus of the exact quotient) for both components
 
 Parity: exact by construction (Fraction arithmetic); pinned in
-``tests/test_oracle_arith.py`` by hand-computed dyadic identities.
+``tests/test_oracle_numbers_arith.py`` by hand-computed dyadic identities.
 """
 
 from __future__ import annotations

@@ -32,7 +32,11 @@ Residual (reading of the unnamed norm in Algorithm 4.1):
 Parity: pinned in ``tests/test_oracle_evaluate.py`` by closed forms
 (Speelpenning's product, x^d - 1 at roots of unity, single monomials),
 by Horner's rule at n = 1, by sympy differentiation of the expanded
-polynomial at n = 2..3, and by central differences in high precision.
+polynomial at n = 2..3, and by central differences in high precision.  The
+scales S, S_iv (and their homotopy forms) are pinned by exact rationals on a
+two-term system at a dyadic point with rational moduli; the residual by
+hand-computed rows (maximum over rows of |Re| + |Im|, divided by the largest
+scale).
 """
 
 from __future__ import annotations

@@ -12,8 +12,9 @@ Gradients by the chain rule written out layer by layer; Adam with bias
 correction.  The flat parameter layout is that of ``synth.policy``.
 
 Parity: pinned in ``tests/test_oracle_mlp.py`` by central finite differences
-in FP64, the value log 2 of the loss at zero logits, and the first Adam step
-(which moves every parameter with a nonzero gradient by lr * sign(g) up to eps).
+in FP64, the value log 2 of the loss at zero logits, the first Adam step
+(which moves every parameter with a nonzero gradient by lr * sign(g) up to eps)
+and three Adam steps written out in exact rationals (bias correction).
 """
 
 from __future__ import annotations

@@ -14,6 +14,8 @@ evaluation in ``oracle.evaluate``.
 Parity: one step is pinned in ``tests/test_oracle_newton.py`` against
 Cramer's rule in exact rationals (n = 2), against sympy's exact solve on a
 3x3 Gaussian-rational system, and by quadratic convergence at a regular root.
+``inv_norm_inf`` and ``cond_inf`` are pinned by the closed-form inverse of a
+complex 2x2 matrix whose row and column sums differ.
 """
 
 from __future__ import annotations

@@ -6,7 +6,7 @@ quad-double library of Hida, Li and Bailey for this representation).  Complex
 numbers are stored ``[2][L]``: real limbs, then imaginary limbs.
 
 Parity: these are definitions (exact rational value of a sum of doubles).
-Pinned in ``tests/test_oracle_numbers.py`` by hand-computed dyadic values.
+Pinned in ``tests/test_oracle_numbers_arith.py`` by hand-computed dyadic values.
 """
 
 from __future__ import annotations

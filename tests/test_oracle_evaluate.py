@@ -210,3 +210,99 @@ def test_homotopy_t_derivative_and_x_derivative_by_differences():
             for i in range(s.n):
                 fd = (a.y[i] - b.y[i]) / (2 * ht)
                 assert abs(fd - r.J[i][v]) <= mpmath.mpf(10) ** -50 * (1 + r.SJ[i][v])
+
+
+# --- componentwise scales and the residual (Algorithm 4.1, "Residual") -------------------
+#
+# Points and coefficients are dyadic with rational moduli (3/4 + i has modulus 5/4,
+# (5 + 12 i)/16 has 13/16), so every scale is an exact rational written out by hand below.
+
+X0 = (Fraction(3, 4), Fraction(1))           # |x0| = 5/4
+X1 = (Fraction(5, 16), Fraction(12, 16))     # |x1| = 13/16
+C1 = (Fraction(3, 4), Fraction(1))           # |c1| = 5/4
+C2 = (Fraction(-2), Fraction(0))             # |c2| = 2
+C3 = (Fraction(0), Fraction(-1, 2))          # |c3| = 1/2
+
+
+def _two_term_system():
+    # f_0 = c1 x0^2 x1 + c2 x1^3 ;  f_1 = c3 x0 + c2 (constant)
+    return build([[(C1, [2, 1]), (C2, [0, 3])], [(C3, [1, 0]), (C2, [0, 0])]], 2)
+
+
+def test_scales_of_a_two_term_system_are_the_exact_rationals():
+    exps, coefs, offs = _two_term_system()
+    x = point([X0, X1])
+    a0, a1 = Fraction(5, 4), Fraction(13, 16)
+    ac1, ac2, ac3 = Fraction(5, 4), Fraction(2), Fraction(1, 2)
+    # S_i = sum_j |c_ij| |x^a_ij|  (a sum of moduli, not the modulus of the sum)
+    S = [ac1 * a0**2 * a1 + ac2 * a1**3, ac3 * a0 + ac2]
+    # S_iv = sum_j |c_ij| a_ijv |x^(a_ij - e_v)|  (the exponent factor included)
+    SJ = [[ac1 * 2 * a0 * a1, ac1 * a0**2 + ac2 * 3 * a1**2], [ac3, Fraction(0)]]
+    with mpmath.workprec(300):
+        for form in ("product", "quotient"):
+            r = eval_system(exps, coefs, offs, x, prec=300, form=form)
+            for i in range(2):
+                assert abs(r.S[i] - mpmath.mpf(S[i].numerator) / S[i].denominator) < mpmath.mpf(2) ** -280
+                for v in range(2):
+                    ref = mpmath.mpf(SJ[i][v].numerator) / SJ[i][v].denominator
+                    assert abs(r.SJ[i][v] - ref) < mpmath.mpf(2) ** -280, (form, i, v)
+
+
+def test_homotopy_scales_add_the_start_system_terms():
+    # S^h_i = |t| S_i + |(1-t) gamma| (|x_i|^d_i + 1);  S^h_ii gains |(1-t) gamma| d_i |x_i|^(d_i-1)
+    exps, coefs, offs = _two_term_system()
+    x = point([X0, X1])
+    gamma = cl((Fraction(3, 4), Fraction(1)))  # |gamma| = 5/4
+    t = 0.25
+    a0, a1 = Fraction(5, 4), Fraction(13, 16)
+    ac1, ac2, ac3 = Fraction(5, 4), Fraction(2), Fraction(1, 2)
+    d = [3, 1]
+    w = (1 - Fraction(1, 4)) * Fraction(5, 4)
+    S = [ac1 * a0**2 * a1 + ac2 * a1**3, ac3 * a0 + ac2]
+    SJ = [[ac1 * 2 * a0 * a1, ac1 * a0**2 + ac2 * 3 * a1**2], [ac3, Fraction(0)]]
+    ax = [a0, a1]
+    Sh = [Fraction(1, 4) * S[i] + w * (ax[i] ** d[i] + 1) for i in range(2)]
+    SJh = [[Fraction(1, 4) * SJ[i][v] + (w * d[i] * ax[i] ** (d[i] - 1) if i == v else 0) for v in range(2)]
+           for i in range(2)]
+    with mpmath.workprec(300):
+        r = eval_homotopy(exps, coefs, offs, gamma, t, x, prec=300)
+        for i in range(2):
+            assert abs(r.S[i] - mpmath.mpf(Sh[i].numerator) / Sh[i].denominator) < mpmath.mpf(2) ** -280
+            for v in range(2):
+                ref = mpmath.mpf(SJh[i][v].numerator) / SJh[i][v].denominator
+                assert abs(r.SJ[i][v] - ref) < mpmath.mpf(2) ** -280, (i, v)
+
+
+def test_residual_is_max_one_norm_over_max_scale():
+    # rho = max_i (|Re h_i| + |Im h_i|) / max_i S_i.  With h = (3 - 4i, 1 + i) and S = (10, 20):
+    # 7/20.  A modulus (5) would give 1/4, a per-row ratio max(7/10, 2/20) 7/10, the sum of
+    # the scales 7/30, the first row's scale 7/10.
+    from oracle.evaluate import EvalResult
+
+    with mpmath.workprec(200):
+        res = EvalResult([0, 1], [mpmath.mpc(3, -4), mpmath.mpc(1, 1)], None, [mpmath.mpf(10), mpmath.mpf(20)], None)
+        assert residual(res) == 0.35
+        # the maximum is over rows: the second row dominates here
+        res = EvalResult([0, 1], [mpmath.mpc(0.5, 0), mpmath.mpc(-2, 3)], None, [mpmath.mpf(40), mpmath.mpf(8)], None)
+        assert residual(res) == 5.0 / 40.0
+        # a zero scale leaves the absolute value
+        res = EvalResult([0], [mpmath.mpc(-0.25, 0.5)], None, [mpmath.mpf(0)], None)
+        assert residual(res) == 0.75
+
+
+def test_residual_of_the_two_term_homotopy_by_hand():
+    # at t = 1, h = f; every value at this dyadic point is an exact Gaussian rational
+    exps, coefs, offs = _two_term_system()
+    x = point([X0, X1])
+    gamma = cl((Fraction(1), Fraction(0)))
+    t = 1.0  # h = f
+    x0, x1 = QC(*X0), QC(*X1)
+    c1, c2, c3 = QC(*C1), QC(*C2), QC(*C3)
+    f0 = c1 * x0 * x0 * x1 + c2 * x1 * x1 * x1
+    f1 = c3 * x0 + c2
+    one = [abs(f.re) + abs(f.im) for f in (f0, f1)]
+    a0, a1 = Fraction(5, 4), Fraction(13, 16)
+    S = [Fraction(5, 4) * a0**2 * a1 + 2 * a1**3, Fraction(1, 2) * a0 + 2]
+    expect = max(one) / max(S)
+    r = eval_homotopy(exps, coefs, offs, gamma, t, x, prec=300)
+    assert residual(r) == pytest.approx(float(expect), rel=1e-15)

@@ -1,6 +1,7 @@
 """Pins for the FP64 network reference: finite differences, loss value, Adam's first step."""
 
 import numpy as np
+import pytest
 
 from oracle.mlp import adam_step, loss, loss_and_grad
 from synth.policy import init_params, n_params, random_batch
@@ -38,3 +39,36 @@ def test_first_adam_step_moves_by_lr_sign():
 
 def test_default_layout_size():
     assert n_params() == 16 * 128 + 128 + 2 * (128 * 128 + 128) + 128 * 6 + 6
+
+
+def test_three_adam_steps_by_hand():
+    # Adam (Kingma & Ba) with bias correction, written out for one scalar parameter and the
+    # gradients 1/2, -1/4, 1 in exact rationals: m_k = b1 m + (1-b1) g, v_k = b2 v + (1-b2) g^2,
+    # p -= lr (m_k / (1 - b1^k)) / (sqrt(v_k / (1 - b2^k)) + eps).  Dropping the bias
+    # correction, using k-1 for k, or putting eps under the root changes steps 2 and 3.
+    from fractions import Fraction as F
+    import math
+
+    b1, b2, lr, eps = F(9, 10), F(999, 1000), 0.1, 1e-8
+    grads = [F(1, 2), F(-1, 4), F(1)]
+    m = v = F(0)
+    p_ref = 1.0
+    expect = []
+    for k, g in enumerate(grads, start=1):
+        m = b1 * m + (1 - b1) * g
+        v = b2 * v + (1 - b2) * g * g
+        mh = m / (1 - b1**k)
+        vh = v / (1 - b2**k)
+        p_ref = p_ref - lr * float(mh) / (math.sqrt(float(vh)) + eps)
+        expect.append(p_ref)
+    # the first two values, also by hand: step 1 moves by lr * (1/2)/(1/2 + eps);
+    # step 2 has m = 1/50, v = 31225/10^8, mh = 2/19, vh = 31225/199900
+    assert expect[0] == pytest.approx(1.0 - 0.1 * 0.5 / (0.5 + 1e-8), rel=1e-15)
+    assert expect[1] == pytest.approx(expect[0] - 0.1 * (2 / 19) / (math.sqrt(31225 / 199900) + 1e-8), rel=1e-15)
+
+    p = np.array([1.0])
+    mm = np.zeros(1)
+    vv = np.zeros(1)
+    for k, g in enumerate(grads, start=1):
+        p, mm, vv = adam_step(p, np.array([float(g)]), mm, vv, k, lr=lr, b1=0.9, b2=0.999, eps=eps)
+        assert p[0] == pytest.approx(expect[k - 1], rel=1e-14, abs=1e-15), k

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 import sympy
 
-from oracle.newton import cond_inf, newton, newton_step
+from oracle.newton import cond_inf, inv_norm_inf, newton, newton_step, newton_tolerance
 from oracle.numbers import QC, vec_mpc
 from synth.systems import CONFIGS, config_system
 from tests.oracle_helpers import DYADIC, build, point
@@ -89,3 +89,40 @@ def test_quadratic_convergence_at_planted_root():
 def test_cond_inf_diagonal():
     J = [[mpmath.mpc(2), 0], [0, mpmath.mpc(0, 0.5)]]
     assert cond_inf(J, 200) == pytest.approx(4.0)
+
+
+def _two_by_two():
+    # J = [[a, b], [c, d]] with entries chosen so that row sums, column sums, the largest
+    # modulus and the |Re| + |Im| norm of the inverse all differ
+    a, b, c, d = mpmath.mpc(2, 0), mpmath.mpc(1, 1), mpmath.mpc(0, 3), mpmath.mpc(3, 4)
+    return a, b, c, d
+
+
+def test_inv_norm_inf_two_by_two_closed_form():
+    # J^-1 = [[d, -b], [-c, a]] / det, so ||J^-1||_inf = max(|d| + |b|, |c| + |a|) / |det|
+    with mpmath.workprec(300):
+        a, b, c, d = _two_by_two()
+        det = a * d - b * c
+        expect = max(abs(d) + abs(b), abs(c) + abs(a)) / abs(det)
+        got = inv_norm_inf([[a, b], [c, d]], 300)
+        assert abs(got - float(expect)) <= 1e-15 * float(expect)
+        # the column-sum norm differs on this matrix, so a transposed sum fails
+        cols = max(abs(d) + abs(c), abs(b) + abs(a)) / abs(det)
+        assert abs(float(cols) - got) > 1e-3
+
+
+def test_cond_inf_two_by_two_closed_form():
+    with mpmath.workprec(300):
+        a, b, c, d = _two_by_two()
+        det = a * d - b * c
+        nJ = max(abs(a) + abs(b), abs(c) + abs(d))
+        nI = max(abs(d) + abs(b), abs(c) + abs(a)) / abs(det)
+        assert cond_inf([[a, b], [c, d]], 300) == pytest.approx(float(nJ * nI), rel=1e-15)
+
+
+def test_newton_tolerance_terms():
+    # 8 n kappa u ||dz|| + 64 u ||J^-1|| max S + 2 u ||z||, u = 2^(-53 L)
+    u = 2.0 ** -106
+    assert newton_tolerance(4, 10.0, 2, 0.5, 2.0) == pytest.approx(8 * 4 * 10.0 * u * 0.5 + 2 * u * 2.0, rel=1e-15)
+    assert newton_tolerance(4, 10.0, 2, 0.5, 2.0, 3.0, 5.0) == pytest.approx(
+        8 * 4 * 10.0 * u * 0.5 + 64 * u * 3.0 * 5.0 + 2 * u * 2.0, rel=1e-15)
