@@ -187,14 +187,53 @@ def _check(status: int):
 
 
 def _ptr(a) -> int:
-    """Address of a contiguous numpy array or torch tensor."""
-    if isinstance(a, np.ndarray):
-        assert a.flags["C_CONTIGUOUS"], "array must be C-contiguous"
-        return a.ctypes.data
+    """Address of a contiguous host numpy array (None passes through)."""
     if a is None:
         return None
-    assert a.is_contiguous(), "tensor must be contiguous"
+    if not isinstance(a, np.ndarray):
+        raise QdpError(1, f"expected a numpy array, got {type(a).__name__}")
+    if not a.flags["C_CONTIGUOUS"]:
+        raise QdpError(1, "array must be C-contiguous")
+    return a.ctypes.data
+
+
+def _dev(a, name: str, numel: int, dtype: str = "float64", nullable: bool = False):
+    """Device address of a torch tensor that a kernel will touch for ``numel``
+    elements of ``dtype``: raises QdpError before any launch unless the tensor
+    is on the GPU, has that dtype, is contiguous and holds at least ``numel``
+    elements (a wrong buffer would otherwise become an out-of-bounds access)."""
+    if a is None:
+        if nullable:
+            return None
+        raise QdpError(1, f"{name}: a device tensor is required")
+    import torch
+
+    if not isinstance(a, torch.Tensor):
+        raise QdpError(1, f"{name}: expected a torch tensor on the GPU, got {type(a).__name__}")
+    if not a.is_cuda:
+        raise QdpError(1, f"{name}: tensor is on {a.device}, not on the GPU")
+    if a.dtype != getattr(torch, dtype):
+        raise QdpError(1, f"{name}: dtype {a.dtype}, expected torch.{dtype}")
+    if not a.is_contiguous():
+        raise QdpError(1, f"{name}: tensor must be contiguous")
+    if a.numel() < numel:
+        raise QdpError(1, f"{name}: {a.numel()} elements, the call touches {numel}")
     return a.data_ptr()
+
+
+def _host_point(x, shape, name: str = "x") -> np.ndarray:
+    """A C-contiguous float64 copy of a host array of exactly ``shape``."""
+    x = np.array(x, dtype=np.float64, copy=True, order="C")
+    if x.shape != tuple(shape):
+        raise QdpError(1, f"{name}: shape {x.shape}, expected {tuple(shape)}")
+    return x
+
+
+def _count(B) -> int:
+    B = int(B)
+    if B < 1:
+        raise QdpError(1, f"batch size {B} < 1")
+    return B
 
 
 def _stream(s) -> Optional[int]:
@@ -217,8 +256,13 @@ class System:
         self._off = np.ascontiguousarray(poly_offsets, dtype=np.int32)
         self._exps = np.ascontiguousarray(exps, dtype=np.uint8)
         self._coefs = np.ascontiguousarray(coefs, dtype=np.float64)
-        if self._coefs.shape[-1] != self.prec:
-            raise ValueError("coefs must be [terms][2][prec]")
+        if self.n < 1 or self._off.shape != (self.n + 1,):
+            raise QdpError(1, f"poly_offsets must hold n + 1 = {self.n + 1} entries")
+        terms = int(self._off[-1])
+        if self._exps.shape != (terms, self.n):
+            raise QdpError(1, f"exps: shape {self._exps.shape}, expected [{terms}][{self.n}]")
+        if self._coefs.shape != (terms, 2, self.prec):
+            raise QdpError(1, f"coefs: shape {self._coefs.shape}, expected [{terms}][2][{self.prec}]")
         h = _P()
         _check(lib().qdp_system_create(self.n, _ptr(self._off), _ptr(self._exps), _ptr(self._coefs), self.prec,
                                        ct.byref(h)))
@@ -285,28 +329,39 @@ class Policy:
         _check(lib().qdp_policy_get_params(self.handle, _ptr(out)))
         return out
 
+    def _batch(self, X, Y=None, M=None):
+        B = _count(X.shape[0]) if hasattr(X, "shape") and len(X.shape) else _count(0)
+        ni, no = int(self.widths[0]), int(self.widths[-1])
+        ptrs = [_dev(X, "X", B * ni, "float32")]
+        if Y is not None or M is not None:
+            ptrs += [_dev(Y, "Y", B * no, "float32"), _dev(M, "M", B * no, "float32")]
+        return B, ptrs
+
     def gradient(self, X, Y, M, grad_out=None, stream=None):
         """Device tensors in; returns the loss (float); gradient into grad_out (device) if given."""
+        B, (px, py, pm) = self._batch(X, Y, M)
+        pg = _dev(grad_out, "grad_out", self.n_params, "float32", nullable=True)
         loss = ct.c_float()
-        _check(lib().qdp_policy_gradient(self.handle, _ptr(X), _ptr(Y), _ptr(M), X.shape[0], _ptr(grad_out),
-                                         ct.byref(loss), _stream(stream)))
+        _check(lib().qdp_policy_gradient(self.handle, px, py, pm, B, pg, ct.byref(loss), _stream(stream)))
         return loss.value
 
     def adam_step(self, grad=None, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=None):
-        _check(lib().qdp_policy_adam_step(self.handle, _ptr(grad), lr, b1, b2, eps, _stream(stream)))
+        pg = _dev(grad, "grad", self.n_params, "float32", nullable=True)
+        _check(lib().qdp_policy_adam_step(self.handle, pg, lr, b1, b2, eps, _stream(stream)))
 
     def train_step(self, X, Y, M, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, want_loss=False, stream=None):
+        B, (px, py, pm) = self._batch(X, Y, M)
         loss = ct.c_float()
-        _check(lib().qdp_policy_train_step(self.handle, _ptr(X), _ptr(Y), _ptr(M), X.shape[0], lr, b1, b2, eps,
+        _check(lib().qdp_policy_train_step(self.handle, px, py, pm, B, lr, b1, b2, eps,
                                            ct.byref(loss) if want_loss else None, _stream(stream)))
         return loss.value if want_loss else None
 
     def forward(self, X, bf16=True, stream=None):
         import torch
 
-        Y = torch.empty((X.shape[0], int(self.widths[-1])), dtype=torch.float32, device=X.device)
-        _check(lib().qdp_policy_forward(self.handle, _ptr(X), X.shape[0], 1 if bf16 else 0, _ptr(Y),
-                                        _stream(stream)))
+        B, (px,) = self._batch(X)
+        Y = torch.empty((B, int(self.widths[-1])), dtype=torch.float32, device=X.device)
+        _check(lib().qdp_policy_forward(self.handle, px, B, 1 if bf16 else 0, Y.data_ptr(), _stream(stream)))
         return Y
 
     def close(self):
@@ -326,8 +381,7 @@ class Policy:
 
 def eval_jacobian(system: System, x: np.ndarray, prec: int, stream=None) -> Tuple[np.ndarray, np.ndarray]:
     n = system.n
-    x = np.ascontiguousarray(x, dtype=np.float64)
-    assert x.shape == (n, 2, prec)
+    x = _host_point(x, (n, 2, prec))
     y = np.zeros((n, 2, prec))
     J = np.zeros((n, n, 2, prec))
     _check(lib().qdp_eval_jacobian(system.handle, _ptr(x), prec, _ptr(y), _ptr(J), _stream(stream)))
@@ -335,13 +389,14 @@ def eval_jacobian(system: System, x: np.ndarray, prec: int, stream=None) -> Tupl
 
 
 def eval_jacobian_dev(system: System, x, prec: int, y, jac, stream=None) -> None:
-    _check(lib().qdp_eval_jacobian_dev(system.handle, _ptr(x), prec, _ptr(y), _ptr(jac), _stream(stream)))
+    v = system.n * 2 * prec
+    px, py, pj = _dev(x, "x", v), _dev(y, "y", v), _dev(jac, "jac", system.n * v)
+    _check(lib().qdp_eval_jacobian_dev(system.handle, px, prec, py, pj, _stream(stream)))
 
 
 def eval_homotopy(h: Homotopy, t: float, x: np.ndarray, prec: int, stream=None):
     n = h.n
-    x = np.ascontiguousarray(x, dtype=np.float64)
-    assert x.shape == (n, 2, prec)
+    x = _host_point(x, (n, 2, prec))
     y = np.zeros((n, 2, prec))
     J = np.zeros((n, n, 2, prec))
     S = np.zeros(n)
@@ -350,19 +405,26 @@ def eval_homotopy(h: Homotopy, t: float, x: np.ndarray, prec: int, stream=None):
 
 
 def eval_homotopy_dev(h: Homotopy, t: float, x, prec: int, y, jac, scale=None, stream=None) -> None:
-    _check(lib().qdp_eval_homotopy_dev(h.handle, float(t), _ptr(x), prec, _ptr(y), _ptr(jac), _ptr(scale),
-                                       _stream(stream)))
+    v = h.n * 2 * prec
+    px, py, pj = _dev(x, "x", v), _dev(y, "y", v), _dev(jac, "jac", h.n * v)
+    ps = _dev(scale, "scale", h.n, nullable=True)
+    _check(lib().qdp_eval_homotopy_dev(h.handle, float(t), px, prec, py, pj, ps, _stream(stream)))
 
 
 def eval_homotopy_batch_dev(h: Homotopy, t: float, x, B: int, prec: int, y, jac, scale=None, stream=None) -> None:
     """B points x [B][n][2][prec] (device) -> y [B][n][2][prec], jac [B][n][n][2][prec], scale [B][n]."""
-    _check(lib().qdp_eval_homotopy_batch_dev(h.handle, float(t), _ptr(x), int(B), prec, _ptr(y), _ptr(jac),
-                                             _ptr(scale), _stream(stream)))
+    B = _count(B)
+    v = B * h.n * 2 * prec
+    px, py, pj = _dev(x, "x", v), _dev(y, "y", v), _dev(jac, "jac", h.n * v)
+    ps = _dev(scale, "scale", B * h.n, nullable=True)
+    _check(lib().qdp_eval_homotopy_batch_dev(h.handle, float(t), px, B, prec, py, pj, ps, _stream(stream)))
 
 
 def newton_batch_dev(h: Homotopy, t: float, x, B: int, prec: int, mode: int = SOLVE_FULL, eps: float = 1e-10,
                      max_it: int = 4, stream=None) -> None:
-    _check(lib().qdp_newton_batch_dev(h.handle, float(t), _ptr(x), int(B), prec, mode, float(eps), int(max_it),
+    B = _count(B)
+    px = _dev(x, "x", B * h.n * 2 * prec)
+    _check(lib().qdp_newton_batch_dev(h.handle, float(t), px, B, prec, mode, float(eps), int(max_it),
                                       _stream(stream)))
 
 
@@ -375,8 +437,7 @@ def last_info_batch(h: Homotopy, prec: int, B: int, stream=None) -> list:
 def newton_step(h: Homotopy, t: float, x: np.ndarray, prec: int, mode: int = SOLVE_FULL, eps: float = 1e-10,
                 max_it: int = 4, stream=None):
     """Returns (new x, info dict)."""
-    x = np.array(x, dtype=np.float64, copy=True, order="C")
-    assert x.shape == (h.n, 2, prec)
+    x = _host_point(x, (h.n, 2, prec))
     info = NewtonInfo()
     _check(lib().qdp_newton_step(h.handle, float(t), _ptr(x), prec, mode, float(eps), int(max_it), ct.byref(info),
                                  _stream(stream)))
@@ -385,7 +446,8 @@ def newton_step(h: Homotopy, t: float, x: np.ndarray, prec: int, mode: int = SOL
 
 def newton_step_dev(h: Homotopy, t: float, x, prec: int, mode: int = SOLVE_FULL, eps: float = 1e-10,
                     max_it: int = 4, stream=None) -> None:
-    _check(lib().qdp_newton_step_dev(h.handle, float(t), _ptr(x), prec, mode, float(eps), int(max_it),
+    px = _dev(x, "x", h.n * 2 * prec)
+    _check(lib().qdp_newton_step_dev(h.handle, float(t), px, prec, mode, float(eps), int(max_it),
                                      _stream(stream)))
 
 
@@ -408,8 +470,7 @@ def default_track_params(**overrides) -> TrackParams:
 def track_path(h: Homotopy, x0: np.ndarray, prec: int, params: Optional[TrackParams] = None, log_cap: int = 0,
                stream=None):
     """Returns (endpoint, stats dict, step log list or None)."""
-    x = np.array(x0, dtype=np.float64, copy=True, order="C")
-    assert x.shape == (h.n, 2, prec)
+    x = _host_point(x0, (h.n, 2, prec), "x0")
     st = TrackStats()
     p = params if params is not None else default_track_params()
     log = (StepRecord * log_cap)() if log_cap > 0 else None
@@ -429,8 +490,9 @@ def track_path(h: Homotopy, x0: np.ndarray, prec: int, params: Optional[TrackPar
 def track_paths(h: Homotopy, x0: np.ndarray, prec: int, params: Optional[TrackParams] = None, stream=None):
     """B paths at once: x0 [B][n][2][prec] start solutions.  Returns (end points, list of stats dicts)."""
     x = np.array(x0, dtype=np.float64, copy=True, order="C")
-    assert x.ndim == 4 and x.shape[1:] == (h.n, 2, prec)
-    nb = x.shape[0]
+    if x.ndim != 4 or x.shape[1:] != (h.n, 2, prec):
+        raise QdpError(1, f"x0: shape {x.shape}, expected [B][{h.n}][2][{prec}]")
+    nb = _count(x.shape[0])
     st = (TrackStats * nb)()
     p = params if params is not None else default_track_params()
     _check(lib().qdp_track_paths(h.handle, _ptr(x), nb, prec, ct.byref(p), st, _stream(stream)))
@@ -441,10 +503,14 @@ def arith_batch(op: str, prec: int, a, b=None, c=None, stream=None):
     """Elementwise multiword op on device tensors (float64, [count][L] or [count][2][L])."""
     import torch
 
-    count = a.shape[0]
+    if op not in ARITH_OPS:
+        raise QdpError(1, f"unknown op {op}")
+    count = int(a.shape[0])
+    pa = _dev(a, "a", max(a.numel(), count))
+    pb = _dev(b, "b", a.numel(), nullable=True)
+    pc = _dev(c, "c", a.numel(), nullable=True)
     out = torch.empty((count, prec), dtype=a.dtype, device=a.device) if op == "pivot" else torch.empty_like(a)
-    _check(lib().qdp_arith_batch(ARITH_OPS[op], prec, count, _ptr(a), _ptr(b), _ptr(c), _ptr(out),
-                                 _stream(stream)))
+    _check(lib().qdp_arith_batch(ARITH_OPS[op], prec, count, pa, pb, pc, out.data_ptr(), _stream(stream)))
     return out
 
 

@@ -7,9 +7,17 @@ name the start root x_v = exp(2 pi i k_v / d_v) whose path ends at z**, and
 confirm the pair by tracking forward.  Also stores the FP64 point of that
 path at t = 1/2 (a starting point for fixed-t Newton timing).
 
+Newton sequences (``newton <name>...``): from the path point at t = 1/2,
+moved off the path by a seeded relative 1e-6, three oracle Newton iterations
+(``oracle.newton.newton_step``), each from the previous oracle iterate rounded
+to the workload's limbs; per iteration the input bits, the oracle's correction
+dz* (8 limbs), its residual and the terms of the one-step tolerance
+(``oracle.newton``: kappa, ||J^-1||, the largest scale).
+
 Calls only ``oracle/`` and ``synth/``.  Usage:
 
     python tests/golden/make_fixtures.py n8_dd n32_dd n64_qd n64_dd n128_dd
+    python tests/golden/make_fixtures.py newton n64_dd n128_dd
 """
 
 from __future__ import annotations
@@ -24,7 +32,11 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
-from oracle.numbers import to_limbs_complex  # noqa: E402
+import mpmath  # noqa: E402
+
+from oracle.evaluate import eval_homotopy  # noqa: E402
+from oracle.newton import cond_inf, inv_norm_inf, newton_step  # noqa: E402
+from oracle.numbers import prec_bits, to_limbs_complex  # noqa: E402
 from oracle.track import F64Homotopy, refine_root, start_root_index, track_f64  # noqa: E402
 from synth.systems import CONFIGS, config_system, make_system  # noqa: E402
 
@@ -89,6 +101,51 @@ def main(names):
         print(name, "k[:4] =", out["start_k"][:4], "seconds", round(out["seconds"], 1), flush=True)
 
 
+NEWTON_T = 0.5
+NEWTON_PERTURB = 1e-6
+NEWTON_ITERS = 3
+
+
+def newton_sequence(name: str) -> dict:
+    cfg = CONFIGS[name]
+    s = config_system(cfg)
+    L = s.L
+    with open(os.path.join(HERE, f"path_{name}.json")) as fh:
+        fix = json.load(fh)
+    base = np.array([complex(a, b) for a, b in fix["x_half_f64"]])
+    rng = np.random.Generator(np.random.PCG64(1000 + cfg.seed))
+    pert = rng.standard_normal(s.n) + 1j * rng.standard_normal(s.n)
+    x = np.stack([to_limbs_complex(mpmath.mpc(v), L) for v in base * (1 + NEWTON_PERTURB * pert)])
+    prec = prec_bits(L)
+    rows = []
+    for k in range(NEWTON_ITERS):
+        t0 = time.time()
+        st = newton_step(s.exps, s.coefs, s.poly_offsets, s.gamma, NEWTON_T, x, form="quotient")
+        hs = eval_homotopy(s.exps, s.coefs, s.poly_offsets, s.gamma, NEWTON_T, x, form="quotient")
+        with mpmath.workprec(prec):
+            row = {
+                "x_limbs": x.tolist(),
+                "dz_limbs": [to_limbs_complex(d, ZSS_LIMBS).tolist() for d in st.dz],
+                "rho": float(st.rho),
+                "kappa": cond_inf(st.J, 300),
+                "jinv": inv_norm_inf(st.J, 300),
+                "h_scale": float(max(hs.S)),
+                "dz_inf": max(float(abs(d)) for d in st.dz),
+                "z_inf": max(float(abs(z)) for z in st.z),
+            }
+            x = np.stack([to_limbs_complex(z, L) for z in st.z])
+        row["seconds"] = time.time() - t0
+        rows.append(row)
+        print(name, "iteration", k, "rho", row["rho"], "|dz|", row["dz_inf"], "kappa", row["kappa"],
+              round(row["seconds"], 1), flush=True)
+    return {
+        "name": name,
+        "source": "written by tests/golden/make_fixtures.py from oracle.newton (newton_step, cond_inf, inv_norm_inf)",
+        "n": s.n, "L": L, "t": NEWTON_T, "perturb": NEWTON_PERTURB, "perturb_seed": 1000 + cfg.seed,
+        "form": "quotient", "iterations": rows,
+    }
+
+
 def main_family(prefix: str, n: int, m: int, E: int, L: int, seeds, refine: bool):
     """Fixtures for a family of systems (learned step control): one JSON with all of them."""
     rows = []
@@ -107,7 +164,12 @@ def main_family(prefix: str, n: int, m: int, E: int, L: int, seeds, refine: bool
 
 
 if __name__ == "__main__":
-    if len(sys.argv) > 1 and sys.argv[1] == "family":
+    if len(sys.argv) > 1 and sys.argv[1] == "newton":
+        for nm in sys.argv[2:]:
+            out = newton_sequence(nm)
+            with open(os.path.join(HERE, f"newton_{nm}.json"), "w") as fh:
+                json.dump(out, fh)
+    elif len(sys.argv) > 1 and sys.argv[1] == "family":
         # family <prefix> <first_seed> <count> <refine 0|1>: n=32 systems shaped like the n32 workload
         prefix, first, count = sys.argv[2], int(sys.argv[3]), int(sys.argv[4])
         refine = len(sys.argv) > 5 and sys.argv[5] == "1"
