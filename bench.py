@@ -95,7 +95,7 @@ def cpu_baseline(sysm, x, t, budget_s: float = 20.0):
     }
 
 
-def track_case(q, name, L):
+def track_case(q, name, L, mode=0):
     """Full path of a stored workload: seconds and correct digits vs the stored z**."""
     import mpmath
     import numpy as np
@@ -108,7 +108,7 @@ def track_case(q, name, L):
     S = q.System.from_synth(s)
     H = q.Homotopy(S, s.gamma)
     x0 = start_root(np.array(fix["degrees"]), np.array(fix["start_k"]), L)
-    z, st, _ = q.track_path(H, x0, L)
+    z, st, _ = q.track_path(H, x0, L, q.default_track_params(mode=mode))
     with mpmath.workprec(800):
         def val(limbs):
             return mpmath.mpc(mpmath.fsum(mpmath.mpf(float(a)) for a in limbs[0]),
@@ -117,10 +117,46 @@ def track_case(q, name, L):
         err = max(abs(val(z[v]) - val(np.array(fix["zss_limbs"][v]))) for v in range(s.n))
         nrm = max(mpmath.mpf(1), max(abs(val(np.array(w))) for w in fix["zss_limbs"]))
         digits = 99 if err == 0 else int(mpmath.floor(-mpmath.log10(err / nrm)))
-    return {"workload": name, "seconds": round(st["seconds"], 4), "correct_digits": digits,
+    return {"workload": name, "solve": "full" if mode == 0 else "mixed",
+            "seconds": round(st["seconds"], 4), "correct_digits": digits,
             "succ_corrections": st["succ_corrections"], "corrections": st["corrections"],
             "newton_iterations": st["newton_iterations"], "avg_step": st["avg_step"], "min_step": st["min_step"],
             "fail": st["fail"]}
+
+
+def limbs_value(limbs):
+    """Exact value of [2][L] limbs as an mpc (at the caller's working precision)."""
+    import mpmath
+
+    return mpmath.mpc(mpmath.fsum(mpmath.mpf(float(a)) for a in limbs[0]),
+                      mpmath.fsum(mpmath.mpf(float(a)) for a in limbs[1]))
+
+
+def newton_vs_oracle(q, name, mode):
+    """One GPU Newton iteration from each point of the stored oracle Newton
+    sequence (tests/golden/newton_<name>.json: three iterations from 1e-6 off
+    the path at t = 1/2): per iteration the oracle's ||dz*||, the GPU's
+    ||z_gpu - (z + dz*)||_inf and that error in units of u ||z|| (u = 2^-106)."""
+    import mpmath
+    import numpy as np
+
+    from synth.systems import CONFIGS, config_system
+
+    with open(os.path.join(ROOT, "tests", "golden", f"newton_{name}.json")) as fh:
+        fix = json.load(fh)
+    s = config_system(CONFIGS[name])
+    H = q.Homotopy(q.System.from_synth(s), s.gamma)
+    rows = []
+    for k, row in enumerate(fix["iterations"]):
+        x = np.array(row["x_limbs"])
+        xg, info = q.newton_step(H, fix["t"], x, 2, mode=mode, eps=0.0, max_it=1)
+        with mpmath.workprec(700):
+            err = max(abs(limbs_value(xg[v]) - limbs_value(x[v]) - limbs_value(np.array(row["dz_limbs"][v])))
+                      for v in range(s.n))
+        rows.append({"iteration": k, "dz_oracle_inf": row["dz_inf"], "err_inf": float(err),
+                     "err_over_u_z": float(err) / (2.0**-106 * row["z_inf"]), "kappa": row["kappa"],
+                     "refine_steps": info["refine_steps"]})
+    return {"workload": name, "solve": "full" if mode == 0 else "mixed", "iterations": rows}
 
 
 def common_support_case(q, steps: int = 1000, warmup: int = 20):
@@ -500,6 +536,17 @@ def main():
             out["paths_batch"] = [track_batch_case(q, "n64_dd", 2, args.batch, paths["n64_dd"])]
         except Exception as e:  # report, never hide, a failing path
             out["paths"] = [{"error": str(e)}]
+    if not args.no_paths and not args.no_extra:
+        # mixed precision (FP64 factorization + double-double refinement) beside the
+        # full double-double solve: error per Newton iteration against the oracle and
+        # the n = 128 path endpoint in both modes
+        try:
+            out["mixed_vs_full"] = {
+                "per_iteration": [newton_vs_oracle(q, nm, md) for nm in ("n64_dd", "n128_dd") for md in (0, 1)],
+                "paths": [track_case(q, "n128_dd", 2, md) for md in (0, 1)],
+            }
+        except Exception as e:  # report, never hide
+            out["mixed_vs_full"] = {"error": str(e)}
     if not args.no_cpu_baseline:
         from synth.systems import config_system
 

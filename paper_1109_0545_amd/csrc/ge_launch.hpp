@@ -1,0 +1,61 @@
+// Elimination launcher shared by the per-precision translation units: the
+// register-resident kernel (ge_reg.hpp) when the augmented matrix fits in one
+// workgroup's registers, else the LDS / global-memory kernel (ge_kernel.hpp).
+#pragma once
+#include "ge_reg.hpp"
+
+namespace qdp {
+
+size_t ge_lds_bytes(int L, int n, bool in_lds);
+
+template <int L, int NW, int NMAX>
+static hipError_t launch_ge_reg(int n, int B, const GeArgs<L> &a, hipStream_t s) {
+  const size_t lds = ge_reg_lds_bytes(L, RegShape<NW, NMAX>::RMAX, n);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ge_reg<L, NW, NMAX>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_ge_reg<L, NW, NMAX>), dim3(B), dim3(64 * NW), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int L>
+static hipError_t launch_ge_L(int n, int B, double *ab, double *scale, double *x, double *dz, NewtonState *st,
+                              hipStream_t s) {
+  GeArgs<L> a{n, ab, scale, x, dz, st};
+  // quad double keeps the LDS kernel: its pivot step (inverse and products in
+  // four limbs) is long enough that the register kernel measured slower
+  if constexpr (L == 1) {
+    if (n <= 64) return launch_ge_reg<1, 16, 64>(n, B, a, s);
+    if (n <= 128) return launch_ge_reg<1, 8, 128>(n, B, a, s);
+  } else if constexpr (L == 2) {
+    if (n <= 16) return launch_ge_reg<2, 4, 16>(n, B, a, s);
+    if (n <= 32) return launch_ge_reg<2, 8, 32>(n, B, a, s);
+    if (n <= 64) return launch_ge_reg<2, 16, 64>(n, B, a, s);
+  }
+  constexpr int NT = (L == 4) ? 512 : 1024;
+  const bool fit = ge_lds_bytes(L, n, true) <= 160 * 1024;
+  // look-ahead rows per lane: 1 up to n = 64, 2 up to 128, 4 up to 256
+  const int rpl = n <= 64 ? 1 : (n <= 128 ? 2 : 4);
+  const size_t lds = ge_lds_bytes(L, n, fit);
+  if (fit) {
+    const void *k = rpl == 1 ? reinterpret_cast<const void *>(&k_ge<L, NT, true, 1>)
+                  : rpl == 2 ? reinterpret_cast<const void *>(&k_ge<L, NT, true, 2>)
+                             : reinterpret_cast<const void *>(&k_ge<L, NT, true, 4>);
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+#define QDP_GE(FIT, RPL) hipLaunchKernelGGL((k_ge<L, NT, FIT, RPL>), dim3(B), dim3(NT), lds, s, a)
+  if (fit) {
+    if (rpl == 1) QDP_GE(true, 1);
+    else if (rpl == 2) QDP_GE(true, 2);
+    else QDP_GE(true, 4);
+  } else {
+    if (rpl == 1) QDP_GE(false, 1);
+    else if (rpl == 2) QDP_GE(false, 2);
+    else QDP_GE(false, 4);
+  }
+#undef QDP_GE
+  return hipGetLastError();
+}
+
+}  // namespace qdp
