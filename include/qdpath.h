@@ -144,6 +144,23 @@ qdp_status qdp_newton_step(const qdp_homotopy *h, double t, double *x, qdp_prec 
 /* Same with x in device memory; asynchronous; read info with qdp_homotopy_last_info. */
 qdp_status qdp_newton_step_dev(const qdp_homotopy *h, double t, double *x, qdp_prec prec, qdp_solve mode,
                                double eps, int32_t max_it, void *hip_stream);
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): qdp_newton_step_dev
+ * with its whole workspace ([A | -h], scales, state, split-evaluation partial
+ * rows, common-support partials, FP64 factors of one point) in a static device
+ * array of 8 MiB per GPU instead of the homotopy's allocated workspace; it calls
+ * no allocating routine.  Results are bit for bit those of qdp_newton_step_dev.
+ *   x        : [n][2][prec] device memory, in/out
+ *   info_dev : nullable; device memory receiving one qdp_newton_info when the
+ *              call's kernels have run (read it after synchronising the stream)
+ * QDP_EINVAL (before any launch) when the system needs more than the 8 MiB (for
+ * example double double at n > 128); the message states the sizes.  Every call on
+ * one GPU shares its array: calls that overlap on a GPU (several streams or
+ * threads) race.  Timing (qdp_set_timing) is not recorded for this entry point.
+ * The array's address is taken on the first call on each device, which must be
+ * current then. */
+qdp_status qdp_newton_step_noalloc_dev(const qdp_homotopy *h, double t, double *x, qdp_prec prec, qdp_solve mode,
+                                       double eps, int32_t max_it, qdp_newton_info *info_dev, void *hip_stream);
 /* Synchronise hip_stream and return the info of the last Newton call on h at precision prec
  * (of its first point for a batch call). */
 qdp_status qdp_homotopy_last_info(const qdp_homotopy *h, qdp_prec prec, qdp_newton_info *info, void *hip_stream);

@@ -32,6 +32,8 @@ from .binding import (  # noqa: F401
     lib,
     newton_step,
     newton_step_dev,
+    newton_step_noalloc_dev,
+    info_from_bytes,
     track_path,
     track_paths,
     version,

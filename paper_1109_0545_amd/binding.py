@@ -137,6 +137,8 @@ SIGNATURES = {
     "qdp_newton_step": (ct.c_int, [_P, ct.c_double, _P, ct.c_int, ct.c_int, ct.c_double, ct.c_int32,
                                    ct.POINTER(NewtonInfo), _P]),
     "qdp_newton_step_dev": (ct.c_int, [_P, ct.c_double, _P, ct.c_int, ct.c_int, ct.c_double, ct.c_int32, _P]),
+    "qdp_newton_step_noalloc_dev": (ct.c_int, [_P, ct.c_double, _P, ct.c_int, ct.c_int, ct.c_double, ct.c_int32,
+                                               _P, _P]),
     "qdp_homotopy_last_info": (ct.c_int, [_P, ct.c_int, ct.POINTER(NewtonInfo), _P]),
     "qdp_eval_homotopy_batch_dev": (ct.c_int, [_P, ct.c_double, _P, ct.c_int32, ct.c_int, _P, _P, _P, _P]),
     "qdp_newton_batch_dev": (ct.c_int, [_P, ct.c_double, _P, ct.c_int32, ct.c_int, ct.c_int, ct.c_double,
@@ -449,6 +451,22 @@ def newton_step_dev(h: Homotopy, t: float, x, prec: int, mode: int = SOLVE_FULL,
     px = _dev(x, "x", h.n * 2 * prec)
     _check(lib().qdp_newton_step_dev(h.handle, float(t), px, prec, mode, float(eps), int(max_it),
                                      _stream(stream)))
+
+
+def newton_step_noalloc_dev(h: Homotopy, t: float, x, prec: int, mode: int = SOLVE_FULL, eps: float = 1e-10,
+                            max_it: int = 4, info=None, stream=None) -> None:
+    """qdp_newton_step_noalloc_dev: x a device tensor (in/out); info an optional
+    device uint8 tensor of at least sizeof(qdp_newton_info) bytes (decode with
+    info_from_bytes after synchronising).  Allocates nothing."""
+    px = _dev(x, "x", h.n * 2 * prec)
+    pi = _dev(info, "info", ct.sizeof(NewtonInfo), "uint8", nullable=True)
+    _check(lib().qdp_newton_step_noalloc_dev(h.handle, float(t), px, prec, mode, float(eps), int(max_it), pi,
+                                             _stream(stream)))
+
+
+def info_from_bytes(raw) -> dict:
+    """A qdp_newton_info from its bytes (host numpy uint8 array)."""
+    return NewtonInfo.from_buffer_copy(bytes(np.asarray(raw, dtype=np.uint8)[: ct.sizeof(NewtonInfo)])).as_dict()
 
 
 def last_info(h: Homotopy, prec: int, stream=None) -> dict:

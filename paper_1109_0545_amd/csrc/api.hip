@@ -395,7 +395,7 @@ extern "C" qdp_status qdp_eval_homotopy(const qdp_homotopy *h, double t, const d
 // only points with mask[b] != 0 run.
 static qdp_status enqueue_newton(qdp_homotopy *h, Workspace *w, int L, double t, double *x_dev, int B, int mode,
                                  double eps, int max_it, hipStream_t st, const double *tb = nullptr,
-                                 const int *mask = nullptr) {
+                                 const int *mask = nullptr, bool allow_timing = true) {
   const qdp_system *f = h->f;
   const int n = f->n;
   HIPCHK(qdp::launch_init_state(w->st, B, eps, max_it, mask, st));
@@ -407,7 +407,7 @@ static qdp_status enqueue_newton(qdp_homotopy *h, Workspace *w, int L, double t,
   const qdp::EvalSplit split{w->part, qdp::kMaxEvalParts, w->suppv, w->bcap};
   qdp::HomArgs ha = hom_args(h, L, t, 1);
   ha.tb = tb;
-  const bool timing = g_timing != 0;
+  const bool timing = g_timing != 0 && allow_timing;
   if (timing) {
     while (w->ev.size() < 3 * (size_t)max_it) {
       hipEvent_t e;
@@ -464,6 +464,97 @@ extern "C" qdp_status qdp_newton_step_dev(const qdp_homotopy *hc, double t, doub
   Workspace *w = nullptr;
   if ((s = ensure_ws(h, (int)prec, 1, &w)) != QDP_OK) return s;
   return enqueue_newton(h, w, (int)prec, t, x, 1, mode, eps, max_it, (hipStream_t)stream);
+}
+
+// ---- Newton's method with no device allocation ---------------------------
+//
+// For callers that cannot allocate device memory (code under stream capture,
+// tight serving loops): the Newton workspace of one point ([A | -h], scales,
+// state, split-evaluation partial rows, common-support partials, FP64
+// factors) lives in one static device array per GPU.  The array's address is
+// taken once per device (with that device current) and kept; host code uses
+// that address, never the array's name.  Every call on a GPU shares its array:
+// calls that overlap on one GPU (other streams, other threads) race.
+constexpr size_t kScratchDoubles = (size_t)1 << 20;  // 8 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxDevices] = {nullptr};
+
+static qdp_status scratch_base(double **out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(QDP_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(QDP_EDEVICE, "no device address for the scratch array");
+    g_scratch_ptr[dev] = static_cast<double *>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return QDP_OK;
+}
+
+__global__ void k_info_from_state(const NewtonState *s, qdp_newton_info *info) {
+  info->iterations = s->iterations;
+  info->success = s->success;
+  info->singular = s->singular;
+  info->nonfinite = s->nonfinite;
+  info->residual_first = s->rho_first;
+  info->residual_last = s->rho;
+  info->cond_est = s->cond_est;
+  info->dz_norm = s->dz_norm;
+  info->refine_err = s->refine_err;
+  info->refine_steps = s->refine_steps;
+  info->pad = 0;
+}
+
+// doubles of scratch one point of (h, L, mode) takes, each part rounded up to 32 doubles
+static size_t scratch_need(const qdp_homotopy *h, int L, int mode, size_t *ab, size_t *scale, size_t *part,
+                           size_t *suppv, size_t *lu, size_t *st) {
+  const int n = h->f->n;
+  auto up = [](size_t d) { return (d + 31) & ~(size_t)31; };
+  *ab = up((size_t)n * (n + 1) * 2 * L);
+  *scale = up((size_t)n);
+  *part = up(qdp::eval_part_doubles(L, n, 1));
+  *suppv = h->f->supp > 0 ? up(qdp::eval_supp_doubles(L, n, h->f->supp)) : 0;
+  *lu = mode == QDP_SOLVE_MIXED_IR ? up((size_t)n * (n + 1) * 2) : 0;
+  *st = up((sizeof(NewtonState) + sizeof(double) - 1) / sizeof(double));
+  return *ab + *scale + *part + *suppv + *lu + *st;
+}
+
+extern "C" qdp_status qdp_newton_step_noalloc_dev(const qdp_homotopy *hc, double t, double *x, qdp_prec prec,
+                                                  qdp_solve mode, double eps, int32_t max_it,
+                                                  qdp_newton_info *info_dev, void *stream) {
+  qdp_status s = newton_checks(hc, t, x, (int)prec, mode, eps, max_it);
+  if (s != QDP_OK) return s;
+  const int L = (int)prec;
+  size_t nab, nsc, npt, nsv, nlu, nst;
+  const size_t need = scratch_need(hc, L, mode, &nab, &nsc, &npt, &nsv, &nlu, &nst);
+  if (need > kScratchDoubles)
+    return fail(QDP_EINVAL, "this system needs " + std::to_string(need * sizeof(double)) +
+                                " bytes of Newton workspace; the no-allocation entry point has " +
+                                std::to_string(kScratchDoubles * sizeof(double)));
+  double *base = nullptr;
+  if ((s = scratch_base(&base)) != QDP_OK) return s;
+  Workspace w;  // views into the scratch array; nothing here is freed or allocated
+  w.L = L;
+  w.bcap = 1;
+  w.ab = base;
+  w.scale = w.ab + nab;
+  w.part = npt > 0 ? w.scale + nsc : nullptr;
+  w.suppv = nsv > 0 ? w.scale + nsc + npt : nullptr;
+  w.lu = nlu > 0 ? w.scale + nsc + npt + nsv : nullptr;
+  w.st = reinterpret_cast<NewtonState *>(w.scale + nsc + npt + nsv + nlu);
+  auto *h = const_cast<qdp_homotopy *>(hc);
+  hipStream_t st = (hipStream_t)stream;
+  if ((s = enqueue_newton(h, &w, L, t, x, 1, mode, eps, max_it, st, nullptr, nullptr, false)) != QDP_OK) return s;
+  if (info_dev) {
+    hipLaunchKernelGGL(k_info_from_state, dim3(1), dim3(1), 0, st, w.st, info_dev);
+    HIPCHK(hipGetLastError());
+  }
+  return QDP_OK;
 }
 
 extern "C" qdp_status qdp_newton_batch_dev(const qdp_homotopy *hc, double t, double *x, int32_t B, qdp_prec prec,
