@@ -72,10 +72,41 @@ def path_point(fix, L):
     return x
 
 
-def cpu_baseline(sysm, x, t, budget_s: float = 20.0):
+def _oracle_rows(args):
+    """Worker of the multi-process oracle leg: h, J and scales of a block of
+    polynomial rows (a fresh interpreter; imports only the oracle)."""
+    import numpy as np
+
+    from oracle.evaluate import eval_homotopy
+
+    exps, coefs, offsets, gamma, t, x, rows = args
+    r = eval_homotopy(np.asarray(exps), np.asarray(coefs), np.asarray(offsets), np.asarray(gamma), t,
+                      np.asarray(x), rows=rows, form="quotient")
+    return r.y, r.J
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(sysm, x, t, budget_s: float = 20.0, max_workers: int = 16):
     """Time the oracle's Newton step (plain mpmath evaluation + lu_solve) on
-    this host, single process, on as many steps as fit in the budget (>= 1)."""
-    from oracle.newton import newton_step
+    this host: single process, then with the evaluation's polynomial rows
+    spread over a pool of worker processes (at most 16, the host share of one
+    GPU; the library linear solve stays in one process).  Each leg runs as
+    many steps as fit in about half the budget (at least one)."""
+    import multiprocessing as mp
+
+    import mpmath
+
+    from oracle.newton import newton_step, solve
 
     t0 = time.perf_counter()
     steps = 0
@@ -85,13 +116,42 @@ def cpu_baseline(sysm, x, t, budget_s: float = 20.0):
         el = time.perf_counter() - t0
         if el > budget_s * 0.5 or steps >= 50:
             break
+    single = steps / el
+    ncpu = os.cpu_count() or 1
+    workers = max(1, min(ncpu, max_workers))
+    n = sysm.n
+    blocks = [list(range(i, n, workers)) for i in range(workers)]
+    args = [(sysm.exps, sysm.coefs, sysm.poly_offsets, sysm.gamma, t, x, rows) for rows in blocks]
+    ctx = mp.get_context("spawn")  # fresh interpreters: nothing of the GPU runtime is inherited
+    with ctx.Pool(workers) as pool:
+        pool.map(_oracle_rows, args[:1])  # start-up and imports outside the timed region
+        t0 = time.perf_counter()
+        psteps = 0
+        while True:
+            parts = pool.map(_oracle_rows, args)
+            J = [None] * n
+            y = [None] * n
+            for rows, (ys, Js) in zip(blocks, parts):
+                for k, i in enumerate(rows):
+                    y[i], J[i] = ys[k], Js[k]
+            with mpmath.workprec(488):
+                solve(J, [-v for v in y], 488)
+            psteps += 1
+            el = time.perf_counter() - t0
+            if el > budget_s * 0.5 or psteps >= 50:
+                break
     return {
-        "value": steps / el,
+        "value": psteps / el,
         "unit": "Newton steps/s",
-        "cores": 1,
+        "cores": workers,
         "kind": "oracle",
-        "sample": f"{steps} oracle Newton step(s) (mpmath at 488 bits: plain evaluation + lu_solve) of the same "
-                  f"n=64 double-double workload at t=0.5, single process, {el:.1f} s",
+        "sample": f"{psteps} oracle Newton step(s) of the same n=64 double-double workload at t=0.5 (mpmath at 488 "
+                  f"bits: plain evaluation with its {n} polynomial rows spread over {workers} worker processes, "
+                  f"then lu_solve in one process), {el:.1f} s; single process: {steps} step(s), "
+                  f"{single:.3f} steps/s",
+        "single_process_value": single,
+        "host_cpu_count": ncpu,
+        "host_cpu_model": cpu_model(),
     }
 
 
@@ -490,7 +550,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "dd",
         "data": "synthetic",
         "config": {
             "workload": "n=64 sparse system, 64 monomials per polynomial, exponents uniform in {0..4}, "

@@ -193,6 +193,13 @@ qdp_status qdp_policy_create(int32_t n_widths, const int32_t *widths, const floa
 void qdp_policy_destroy(qdp_policy *p);
 /* Synchronises the device and copies the FP32 parameters to host memory. */
 qdp_status qdp_policy_get_params(const qdp_policy *p, float *params);
+/* Write the network to a file: widths, FP32 parameters and the feature
+ * normalisation (not the Adam moments); little-endian binary with an 8-byte
+ * tag.  QDP_EINVAL if the file cannot be written. */
+qdp_status qdp_policy_save(const qdp_policy *p, const char *path);
+/* Create a network from a file written by qdp_policy_save (as qdp_policy_create;
+ * Adam moments start at zero).  QDP_EINVAL for a missing or malformed file. */
+qdp_status qdp_policy_load(const char *path, qdp_policy **out);
 /* Loss and gradient of a batch (device pointers X [B][w_0] raw features, Y, M [B][w_last]).
  * grad_out: device [n_params] or NULL (kept internally for qdp_policy_adam_step); loss_out: host
  * or NULL (non-NULL synchronises the stream).  1 <= B <= 65536. */

@@ -155,6 +155,8 @@ SIGNATURES = {
     "qdp_policy_create": (ct.c_int, [ct.c_int32, _P, _P, _P, _P, ct.POINTER(_P)]),
     "qdp_policy_destroy": (None, [_P]),
     "qdp_policy_get_params": (ct.c_int, [_P, _P]),
+    "qdp_policy_save": (ct.c_int, [_P, ct.c_char_p]),
+    "qdp_policy_load": (ct.c_int, [ct.c_char_p, ct.POINTER(_P)]),
     "qdp_policy_gradient": (ct.c_int, [_P, _P, _P, _P, ct.c_int32, _P, _P, _P]),
     "qdp_policy_adam_step": (ct.c_int, [_P, _P, ct.c_float, ct.c_float, ct.c_float, ct.c_float, _P]),
     "qdp_policy_train_step": (ct.c_int, [_P, _P, _P, _P, ct.c_int32, ct.c_float, ct.c_float, ct.c_float,
@@ -325,6 +327,30 @@ class Policy:
         self.handle = h
         self.n_params = p.size
         self.feat_mean, self.feat_std = mu, sd
+
+    @classmethod
+    def load(cls, path: str) -> "Policy":
+        """qdp_policy_load: a network from a file written by save()."""
+        h = _P()
+        _check(lib().qdp_policy_load(os.fsencode(path), ct.byref(h)))
+        self = cls.__new__(cls)
+        self.handle = h
+        # widths and normalisation back from the file's header (read by the library above)
+        with open(path, "rb") as fh:
+            fh.read(8)
+            nw = int(np.frombuffer(fh.read(4), dtype="<i4")[0])
+            self.widths = np.frombuffer(fh.read(4 * nw), dtype="<i4").astype(np.int32)
+        self.n_params = int(sum(o * i + o for i, o in zip(self.widths[:-1], self.widths[1:])))
+        with open(path, "rb") as fh:
+            fh.seek(12 + 4 * nw + 4 * self.n_params)
+            w0 = int(self.widths[0])
+            self.feat_mean = np.frombuffer(fh.read(4 * w0), dtype="<f4").copy()
+            self.feat_std = np.frombuffer(fh.read(4 * w0), dtype="<f4").copy()
+        return self
+
+    def save(self, path: str) -> None:
+        """qdp_policy_save: widths, parameters and feature normalisation to a file."""
+        _check(lib().qdp_policy_save(self.handle, os.fsencode(path)))
 
     def params(self) -> np.ndarray:
         out = np.zeros(self.n_params, dtype=np.float32)

@@ -15,6 +15,7 @@
 
 #include "../../include/qdpath.h"
 #include "common.hpp"
+#include "ctl_features.hpp"
 
 namespace qdp {
 hipError_t launch_ge_scaled(int L, int n, int B, double *ab, double *scale, double *x, double *dz, NewtonState *st,
@@ -31,6 +32,10 @@ hipError_t launch_predict(int L, int n, const double *x, const double *xprev, co
 hipError_t launch_blend_label(int L, int n, const double *x, const double *xprev, const double *xprev2,
                               const double *xcorr, double s1, double q1, double q2, double *aux, hipStream_t s);
 hipError_t launch_copy(double *dst, const double *src, size_t count, hipStream_t s);
+hipError_t launch_ctl_features(const CtlFeatIn &h, const NewtonState *st, const double *aux, float *f,
+                               hipStream_t s);
+hipError_t launch_stage_readback(const NewtonState *st, const double *aux, const float *pout, StageReadback *rb,
+                                 hipStream_t s);
 hipError_t launch_mixed_solve(int n, int B, double *ab, double *scale, double *x, NewtonState *st, double *lu,
                               double *work, int refinements, hipStream_t s);
 }  // namespace qdp
@@ -96,6 +101,9 @@ struct Workspace {
   double *work = nullptr;   // mixed precision scratch
   NewtonState *st = nullptr;  // [bcap]
   double *aux = nullptr;       // [4] predictor distance, blend-label sums
+  float *pfeat = nullptr;      // [16] controller features, then [8] network outputs
+  qdp::StageReadback *rb_dev = nullptr;   // a corrector stage's results, gathered
+  qdp::StageReadback *rb_host = nullptr;  // pinned host copy of rb_dev
   std::vector<hipEvent_t> ev;  // timing: 3 events per iteration (before eval, between, after solve)
   int timed_its = 0;
 };
@@ -135,6 +143,9 @@ static qdp_status ensure_ws(qdp_homotopy *h, int L, int B, Workspace **out) {
     HIPCHK(hipMalloc(&w.y, (size_t)n * e * sizeof(double)));
     HIPCHK(hipMalloc(&w.jac, (size_t)n * n * e * sizeof(double)));
     HIPCHK(hipMalloc(&w.aux, 4 * sizeof(double)));
+    HIPCHK(hipMalloc(&w.pfeat, 24 * sizeof(float)));
+    HIPCHK(hipMalloc(&w.rb_dev, sizeof(qdp::StageReadback)));
+    HIPCHK(hipHostMalloc(&w.rb_host, sizeof(qdp::StageReadback), hipHostMallocDefault));
     if (L == 2) HIPCHK(hipMalloc(&w.work, (size_t)n * 8 * 2 * sizeof(double)));
     w.L = L;
   }
@@ -167,6 +178,9 @@ static void free_ws(Workspace &w) {
   hipFree(w.jac);
   hipFree(w.work);
   hipFree(w.aux);
+  hipFree(w.pfeat);
+  hipFree(w.rb_dev);
+  hipHostFree(w.rb_host);
   for (auto &e : w.ev) hipEventDestroy(e);
   w = Workspace();
 }
@@ -709,33 +723,30 @@ struct CtlHistory {
   double rho_first = 1.0, rho_last = 1.0, cond = 1.0, dz_first = 0.0, znorm = 1.0, pred_dist = 0.0;
 };
 
-static double lg(double v, double lo) { return std::log10(std::max(v, lo)); }
-
-// The 16 inputs of the step-size network in the state after an accepted step.
-static void features(const CtlHistory &h, double t, float *f) {
-  const double zn = std::max(h.znorm, 1.0);
+// the controller's state after the last accepted step, for the shared feature function
+static qdp::CtlFeatIn feat_in(const CtlHistory &h, double t) {
+  qdp::CtlFeatIn f;
+  f.lam[0] = h.lam_acc[0];
+  f.lam[1] = h.lam_acc[1];
+  f.lam[2] = h.lam_acc[2];
+  f.iters = h.iters;
+  f.rho_first = h.rho_first;
+  f.rho_last = h.rho_last;
+  f.cond = h.cond;
+  f.dz_first = h.dz_first;
+  f.znorm = h.znorm;
+  f.pred_dist = h.pred_dist;
+  f.t = t;
+  f.run = h.run;
   int rej = 0;
   for (int k = 0; k < 8 && k < h.attempts; ++k) rej += ((h.recent >> k) & 1u) ? 0 : 1;
-  const double v[16] = {
-      std::log2(h.lam_acc[0] / 0.01),
-      std::log2(h.lam_acc[1] / 0.01),
-      std::log2(h.lam_acc[2] / 0.01),
-      (double)h.iters,
-      lg(h.rho_first, 1e-40) / 10.0,
-      lg(h.rho_last, 1e-40) / 10.0,
-      lg(h.cond, 1.0) / 5.0,
-      t,
-      lg(1.0 - t, 1e-16),
-      lg(h.znorm, 1e-300),
-      lg(h.pred_dist / zn, 1e-40) / 10.0,
-      lg(h.dz_first / zn, 1e-40) / 10.0,
-      std::min(h.run, 10) / 10.0,
-      rej / 8.0,
-      (lg(h.dz_first, 1e-300) - lg(h.pred_dist, 1e-300)) / 10.0,
-      std::min<double>((double)h.accepted, 1000.0) / 1000.0,
-  };
-  for (int k = 0; k < 16; ++k) f[k] = (float)v[k];
+  f.rejected = rej;
+  f.accepted = h.accepted;
+  return f;
 }
+
+// The 16 inputs of the step-size network in the state after an accepted step.
+static void features(const CtlHistory &h, double t, float *f) { qdp::ctl_features(feat_in(h, t), f); }
 
 }  // namespace
 
@@ -787,7 +798,7 @@ extern "C" qdp_status qdp_track_path(const qdp_homotopy *hc, double *x, qdp_prec
   NewtonState ns;
   double aux[4] = {0, 0, 0, 0};
   CtlHistory hist;
-  float feat[16];
+  float pout[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // network outputs for the state the last main stage led to
   auto push = [&](const qdp_step_record &r) {
     if (log && nlog < log_cap) log[nlog++] = r;
   };
@@ -801,8 +812,11 @@ extern "C" qdp_status qdp_track_path(const qdp_homotopy *hc, double *x, qdp_prec
     }
   };
   // one corrector stage from the current accepted point with step `step`;
-  // wq weights the quadratic predictor against the secant (0 = secant)
-  auto correct = [&](double step, double wq, double &tn_out) -> qdp_status {
+  // wq weights the quadratic predictor against the secant (0 = secant).
+  // infer: run the network, on the device and before the stage is read back,
+  // on the state this stage leads to if the Newton test accepts it (the only
+  // case in which the next step asks the network)
+  auto correct = [&](double step, double wq, double &tn_out, bool infer) -> qdp_status {
     const double tn = (t + step >= 1.0) ? 1.0 : t + step;
     tn_out = tn;
     double s1, q1, q2;
@@ -815,9 +829,25 @@ extern "C" qdp_status qdp_track_path(const qdp_homotopy *hc, double *x, qdp_prec
     HIPCHK(qdp::launch_predict(L, n, w->x, w->xprev, w->xprev2, c1, c2, w->xw, w->aux, st));
     qdp_status e = enqueue_newton(h, w, L, tn, w->xw, 1, p.mode, p.eps_path, p.max_it_path, st);
     if (e != QDP_OK) return e;
-    HIPCHK(hipMemcpyAsync(&ns, w->st, sizeof(ns), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(aux, w->aux, sizeof(aux), hipMemcpyDeviceToHost, st));
+    if (infer) {
+      CtlHistory next = hist;  // the history after accepting this stage
+      next.lam_acc[2] = hist.lam_acc[1];
+      next.lam_acc[1] = hist.lam_acc[0];
+      next.lam_acc[0] = step;
+      next.recent = (hist.recent << 1) | 1u;
+      next.attempts = hist.attempts + 1;
+      next.accepted = succ + 1;
+      next.run = run + 1;
+      HIPCHK(qdp::launch_ctl_features(feat_in(next, tn), w->st, w->aux, w->pfeat, st));
+      if ((e = qdp_policy_forward(p.policy, w->pfeat, 1, 1, w->pfeat + 16, st)) != QDP_OK) return e;
+    }
+    // one gathered record, one copy into pinned memory, one synchronisation
+    HIPCHK(qdp::launch_stage_readback(w->st, w->aux, infer ? w->pfeat + 16 : nullptr, w->rb_dev, st));
+    HIPCHK(hipMemcpyAsync(w->rb_host, w->rb_dev, sizeof(qdp::StageReadback), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    ns = w->rb_host->st;
+    std::memcpy(aux, w->rb_host->aux, sizeof(aux));
+    if (infer) std::memcpy(pout, w->rb_host->pout, sizeof(pout));
     return QDP_OK;
   };
 
@@ -834,7 +864,7 @@ extern "C" qdp_status qdp_track_path(const qdp_homotopy *hc, double *x, qdp_prec
       for (int k = 0; k < 5; ++k) {
         const double step = std::min(hist.lam_acc[0] * std::ldexp(1.0, k - 1), 1.0 - t);
         double tn;
-        if ((s = correct(step, 1.0, tn)) != QDP_OK) return s;
+        if ((s = correct(step, 1.0, tn, false)) != QDP_OK) return s;
         ++probes;
         if (ns.success) {
           rec.probe_ok |= 1 << k;
@@ -855,10 +885,9 @@ extern "C" qdp_status qdp_track_path(const qdp_homotopy *hc, double *x, qdp_prec
     double wgt = plain_wq;
     from_policy = false;
     if (learned && npts >= 2 && run > 0) {
-      // after a success: the network proposes the multiplier and the secant weight
-      features(hist, t, feat);
-      float out[8];
-      if ((s = qdp_policy_infer_host(p.policy, feat, out, stream)) != QDP_OK) return s;
+      // after a success: the network proposes the multiplier and the secant
+      // weight; it ran on this state right after the stage that reached it
+      const float *out = pout;
       int best = -1;
       double best_score = -1.0;
       for (int k = 0; k < 5; ++k) {
@@ -877,7 +906,7 @@ extern "C" qdp_status qdp_track_path(const qdp_homotopy *hc, double *x, qdp_prec
       from_policy = true;
     }
     double tn;
-    if ((s = correct(step, wgt, tn)) != QDP_OK) return s;
+    if ((s = correct(step, wgt, tn, learned)) != QDP_OK) return s;
     ++corr;
     nit += ns.iterations;
     const bool ok = ns.success != 0;

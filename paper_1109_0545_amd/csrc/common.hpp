@@ -81,6 +81,14 @@ struct NewtonState {
   double xnorm;      // ||x||_inf after the last update
 };
 
+// What the tracker reads back after a corrector stage, gathered on the device
+// into one record so that one copy brings it to (pinned) host memory.
+struct StageReadback {
+  NewtonState st;
+  double aux[4];   // predictor distance, blend-label sums
+  float pout[8];   // the step-size network's outputs (learned control)
+};
+
 // Launchers (defined per translation unit; return hipError_t).  A launch
 // covers B independent points: x holds B points bx doubles apart, gate B
 // Newton states (nullable).

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
 #include <algorithm>
 #include <cstring>
 #include <mutex>
@@ -166,9 +167,24 @@ __device__ inline unsigned short to_bf16(float x) {
 }
 __device__ inline float from_bf16(unsigned short h) { return __uint_as_float(((unsigned int)h) << 16); }
 
-__global__ void k_to_bf16(long count, const float *p, unsigned short *out) {
-  const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < count) out[q] = to_bf16(p[q]);
+// BF16 copy for inference with each layer's weights transposed to [in][out]
+// (the bias [out] follows as in the FP32 layout), so that at a fixed input k
+// the threads of a workgroup, one per output, read consecutive weights.
+__global__ void k_to_bf16_t(int nl, const int *widths, const float *p, unsigned short *out) {
+  long off = 0;
+  for (int l = 0; l < nl; ++l) {
+    const int in = widths[l], o = widths[l + 1];
+    const long nw = (long)in * o;
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < nw + o; q += (long)gridDim.x * blockDim.x) {
+      if (q < nw) {
+        const long j = q / in, k = q - j * in;  // source [j][k]
+        out[off + k * o + j] = to_bf16(p[off + q]);
+      } else {
+        out[off + q] = to_bf16(p[off + q]);
+      }
+    }
+    off += nw + o;
+  }
 }
 
 // Inference of one input row per block: weights in BF16 (or FP32), activations
@@ -188,13 +204,24 @@ __global__ __launch_bounds__(256) void k_infer(int B, int nl, const int *widths,
   for (int l = 0; l < nl; ++l) {
     const int in = widths[l], out = widths[l + 1];
     for (int j = threadIdx.x; j < out; j += blockDim.x) {
+      // BF16 weights are stored [in][out] (k_to_bf16_t), FP32 ones [out][in];
+      // weights are loaded KC at a time ahead of their products so that the
+      // loads overlap instead of each waiting for the previous product
+      auto wt = [&](int k) {
+        return BF16 ? from_bf16(static_cast<const unsigned short *>(params)[off + (long)k * out + j])
+                    : static_cast<const float *>(params)[off + (long)j * in + k];
+      };
+      constexpr int KC = 16;
       float s = 0.0f;
-      for (int k = 0; k < in; ++k) {
-        const long q = off + (long)j * in + k;
-        const float w = BF16 ? from_bf16(static_cast<const unsigned short *>(params)[q])
-                             : static_cast<const float *>(params)[q];
-        s = __builtin_fmaf(w, cur[k], s);
+      int k = 0;
+      for (; k + KC <= in; k += KC) {
+        float wv[KC];
+#pragma unroll
+        for (int u = 0; u < KC; ++u) wv[u] = wt(k + u);
+#pragma unroll
+        for (int u = 0; u < KC; ++u) s = __builtin_fmaf(wv[u], cur[k + u], s);
       }
+      for (; k < in; ++k) s = __builtin_fmaf(wt(k), cur[k], s);
       const long qb = off + (long)out * in + j;
       s += BF16 ? from_bf16(static_cast<const unsigned short *>(params)[qb]) : static_cast<const float *>(params)[qb];
       nxt[j] = (l < nl - 1) ? fmaxf(s, 0.0f) : s;
@@ -358,6 +385,57 @@ static qdp_status train_forward(qdp_policy *p, const float *X, int B, hipStream_
   return QDP_OK;
 }
 
+// Policy file: the 8 bytes "QDPPOL1\0", int32 n_widths, int32 widths[n_widths],
+// float params (flat layout), float feature mean[w_0], float feature std[w_0];
+// little-endian, as the host writes them.  Adam moments are not stored.
+static const char kPolicyMagic[8] = {'Q', 'D', 'P', 'P', 'O', 'L', '1', '\0'};
+
+extern "C" qdp_status qdp_policy_save(const qdp_policy *pc, const char *path) {
+  if (!pc || !path) return qdp_policy_fail(QDP_EINVAL, "NULL argument");
+  std::vector<float> params((size_t)pc->np);
+  qdp_status s = qdp_policy_get_params(pc, params.data());
+  if (s != QDP_OK) return s;
+  FILE *f = std::fopen(path, "wb");
+  if (!f) return qdp_policy_fail(QDP_EINVAL, std::string("cannot open ") + path + " for writing");
+  const int32_t nw = (int32_t)pc->w.size();
+  std::vector<int32_t> w(pc->w.begin(), pc->w.end());
+  bool ok = std::fwrite(kPolicyMagic, 1, 8, f) == 8 && std::fwrite(&nw, sizeof nw, 1, f) == 1 &&
+            std::fwrite(w.data(), sizeof(int32_t), w.size(), f) == w.size() &&
+            std::fwrite(params.data(), sizeof(float), params.size(), f) == params.size() &&
+            std::fwrite(pc->mean, sizeof(float), (size_t)w[0], f) == (size_t)w[0] &&
+            std::fwrite(pc->sd, sizeof(float), (size_t)w[0], f) == (size_t)w[0];
+  ok = (std::fclose(f) == 0) && ok;
+  return ok ? QDP_OK : qdp_policy_fail(QDP_EINVAL, std::string("write to ") + path + " failed");
+}
+
+extern "C" qdp_status qdp_policy_load(const char *path, qdp_policy **out) {
+  if (!path || !out) return qdp_policy_fail(QDP_EINVAL, "NULL argument");
+  *out = nullptr;
+  FILE *f = std::fopen(path, "rb");
+  if (!f) return qdp_policy_fail(QDP_EINVAL, std::string("cannot open ") + path);
+  char magic[8];
+  int32_t nw = 0;
+  bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kPolicyMagic, 8) == 0 &&
+            std::fread(&nw, sizeof nw, 1, f) == 1 && nw >= 2 && nw <= 9;
+  std::vector<int32_t> w(ok ? (size_t)nw : 0);
+  if (ok) ok = std::fread(w.data(), sizeof(int32_t), w.size(), f) == w.size();
+  if (ok)
+    for (int32_t x : w) ok = ok && x >= 1 && x <= 256;
+  std::vector<float> params, mean, sd;
+  if (ok) {
+    std::vector<int> wi(w.begin(), w.end());
+    params.resize((size_t)offset_of(wi, nw - 1));
+    mean.resize((size_t)w[0]);
+    sd.resize((size_t)w[0]);
+    ok = std::fread(params.data(), sizeof(float), params.size(), f) == params.size() &&
+         std::fread(mean.data(), sizeof(float), mean.size(), f) == mean.size() &&
+         std::fread(sd.data(), sizeof(float), sd.size(), f) == sd.size();
+  }
+  std::fclose(f);
+  if (!ok) return qdp_policy_fail(QDP_EINVAL, std::string(path) + " is not a policy file of this library");
+  return qdp_policy_create(nw, w.data(), params.data(), mean.data(), sd.data(), out);
+}
+
 extern "C" qdp_status qdp_policy_gradient(qdp_policy *p, const float *X, const float *Y, const float *Mk,
                                           int32_t B, float *grad_out, float *loss_out, void *stream) {
   if (!p || !X || !Y || !Mk) return qdp_policy_fail(QDP_EINVAL, "NULL argument");
@@ -433,7 +511,7 @@ extern "C" qdp_status qdp_policy_train_step(qdp_policy *p, const float *X, const
 
 static qdp_status refresh_bf16(qdp_policy *p, hipStream_t s) {
   if (!p->bf16_stale) return QDP_OK;
-  hipLaunchKernelGGL(qdp::k_to_bf16, dim3((unsigned)((p->np + 255) / 256)), dim3(256), 0, s, p->np, p->d_p, p->d_pbf);
+  hipLaunchKernelGGL(qdp::k_to_bf16_t, dim3(64), dim3(256), 0, s, (int)p->w.size() - 1, p->d_w, p->d_p, p->d_pbf);
   PCHK(hipGetLastError());
   p->bf16_stale = false;
   return QDP_OK;

@@ -3,6 +3,7 @@
 
 #include "common.hpp"
 #include "ge_kernel.hpp"
+#include "ctl_features.hpp"
 
 namespace qdp {
 using namespace mw;
@@ -174,6 +175,39 @@ hipError_t launch_blend_label(int L, int n, const double *x, const double *xprev
     case 4: hipLaunchKernelGGL(k_blend_label<4>, g, b, 0, s, n, x, xprev, xprev2, xcorr, s1, q1, q2, aux); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+// The controller's features of the state a corrector stage leads to if the
+// Newton test accepts it: the host-known part in `h`, the stage's Newton
+// results from its state and the predictor distance from aux[0].
+__global__ void k_ctl_features(CtlFeatIn h, const NewtonState *st, const double *aux, float *f) {
+  h.iters = st->iterations;
+  h.rho_first = st->rho_first;
+  h.rho_last = st->rho;
+  h.cond = st->cond_est;
+  h.dz_first = st->dz_first;
+  h.znorm = st->xnorm;
+  h.pred_dist = aux[0];
+  ctl_features(h, f);
+}
+
+hipError_t launch_ctl_features(const CtlFeatIn &h, const NewtonState *st, const double *aux, float *f,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_ctl_features, dim3(1), dim3(1), 0, s, h, st, aux, f);
+  return hipGetLastError();
+}
+
+__global__ void k_stage_readback(const NewtonState *st, const double *aux, const float *pout, StageReadback *rb) {
+  const int t = threadIdx.x;
+  if (t == 0) rb->st = *st;
+  if (t < 4) rb->aux[t] = aux[t];
+  if (t < 8) rb->pout[t] = pout ? pout[t] : 0.0f;
+}
+
+hipError_t launch_stage_readback(const NewtonState *st, const double *aux, const float *pout, StageReadback *rb,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_stage_readback, dim3(1), dim3(64), 0, s, st, aux, pout, rb);
   return hipGetLastError();
 }
 

@@ -30,6 +30,8 @@ def check_eval(sysm, L, x, rows=None, form="product"):
         worst = max(worst, err_over_scale(y[i], ref.y[r], ref.S[r]))
         for v in range(sysm.n):
             worst = max(worst, err_over_scale(J[i, v], ref.J[r][v], ref.SJ[r][v]))
+    say(f"  worst |d| / S = {worst:.3e} = {worst / 2.0 ** (-53 * L):.2f} u (bound {TAU[L]:.0e} = "
+        f"{TAU[L] / 2.0 ** (-53 * L):.0f} u)")
     assert worst <= TAU[L], worst
     return worst
 
@@ -91,6 +93,42 @@ def test_eval_variable_term_counts_and_constants():
     check_eval(s, 2, point([(Fraction(3, 4), Fraction(-1, 2)), (Fraction(5, 8), 0), (0, Fraction(7, 8))]))
 
 
+def zero_coordinate_system():
+    """n = 7 with x_0 = x_3 = x_6 = 0 exactly: each monomial holds at most one of
+    the zero coordinates (first, middle or last variable of the walk), with
+    exponent 1 (its partial is the product of the other factors) or 2 (its
+    partial vanishes), beside nonzero coordinates; some monomials hold none."""
+    from fractions import Fraction
+
+    n = 7
+    polys = []
+    for i in range(n):
+        terms = []
+        for k in range(8):
+            a = [0] * n
+            for v in (1, 2, 4, 5):
+                a[v] = (i + k + v) % 3
+            z = (0, 3, 6, None)[k % 4]
+            if z is not None:
+                a[z] = 1 + (k // 4 + i) % 2
+            terms.append(((Fraction(k + 1, 8), Fraction(i - k, 16)), a))
+        polys.append(terms)
+    exps, coefs, offs = build(polys, n, 2)
+    from synth.systems import System
+
+    s = System(n, 2, offs, exps, coefs, np.zeros((2, 2)), np.zeros((n, 2, 2)), np.zeros(n, np.int64),
+               np.zeros(n, np.int32))
+    x = point([(0, 0), (Fraction(3, 4), Fraction(1, 8)), (Fraction(-5, 8), Fraction(1, 2)), (0, 0),
+               (Fraction(7, 8), Fraction(-1, 4)), (Fraction(1, 2), Fraction(3, 8)), (0, 0)])
+    return s, x
+
+
+def test_eval_exact_zero_coordinates():
+    # a zero factor inside the Speelpenning walk, against the plain product form
+    s, x = zero_coordinate_system()
+    check_eval(s, 2, x)
+
+
 def test_speelpenning_closed_form_on_gpu():
     # f_0 = prod_v x_v at x_v = r: every partial is r^(n-1)
     import paper_1109_0545_amd as q
@@ -131,13 +169,18 @@ def test_eval_homotopy_n32(t):
 def check_homotopy_rows(s, L, t, x, ref, y, J, sc):
     """tau times the componentwise scale, plus the rounding bound of the
     start-system power (binary powering in working precision) on h_i and J_ii."""
+    u = 2.0 ** (-53 * L)
+    worst = 0.0  # |d| / (u S): the observed error in units of the componentwise scale
     for r, i in enumerate(ref.rows):
         bv, bd = start_power_bounds(L, t, s.gamma, x[i], int(s.degrees[i]))
+        worst = max(worst, err_over_scale(y[i], ref.y[r], u * ref.S[r]))
         assert err_over_scale(y[i], ref.y[r], TAU[L] * ref.S[r] + bv) <= 1.0
         assert abs(sc[i] - float(ref.S[r])) <= 1e-12 * float(ref.S[r])
         for v in range(s.n):
             extra = bd if v == i else 0.0
+            worst = max(worst, err_over_scale(J[i, v], ref.J[r][v], u * ref.SJ[r][v]))
             assert err_over_scale(J[i, v], ref.J[r][v], TAU[L] * ref.SJ[r][v] + extra) <= 1.0
+    say(f"  homotopy rows: worst |d| / (u S) = {worst:.2f} (bound {TAU[L] / u:.0f} plus the start-power term)")
 
 
 def test_eval_dev_variant_matches_host_variant():

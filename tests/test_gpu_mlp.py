@@ -102,3 +102,27 @@ def test_policy_argument_checks():
         q.Policy([16], np.zeros(0), np.zeros(16), np.ones(16))
     with pytest.raises(q.QdpError):
         q.Policy(LAYERS, init_params(1), np.zeros(16), np.zeros(16))  # std must be > 0
+
+
+def test_policy_save_load_round_trip(tmp_path):
+    # qdp_policy_save / qdp_policy_load: same widths, parameters, normalisation
+    # and forward outputs; a malformed file is rejected
+    import paper_1109_0545_amd as q
+
+    pol, p = _policy(17)
+    path = str(tmp_path / "pol.bin")
+    say("policy save/load")
+    pol.save(path)
+    back = q.Policy.load(path)
+    assert np.array_equal(back.widths, pol.widths)
+    assert np.array_equal(back.params(), pol.params())
+    assert np.array_equal(back.feat_mean, pol.feat_mean) and np.array_equal(back.feat_std, pol.feat_std)
+    X, _, _ = random_batch(18, 9)
+    xd = _dev(X.astype(np.float32).astype(np.float64))
+    a = pol.forward(xd, bf16=False).cpu().numpy()
+    b = back.forward(xd, bf16=False).cpu().numpy()
+    assert np.array_equal(a, b)
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(b"not a policy")
+    with pytest.raises(q.QdpError):
+        q.Policy.load(str(bad))

@@ -43,6 +43,7 @@ def check_step(s, x, t, L, xg, info, form):
         zn = max(float(abs(z)) for z in ref.z)
         tol = newton_tolerance(s.n, kappa, L, dzn, zn, jinv, float(max(hs.S)))
         err = max(float(abs(mpc_of(xg[v]) - ref.z[v])) for v in range(s.n))
+    say(f"  one step: |z_gpu - z_oracle| = {err:.3e}, bound {tol:.3e} (ratio {err / tol:.2e}), kappa {kappa:.3g}")
     assert err <= tol, (err, tol, kappa)
     # the residual agrees to FP64 unless it sits at the rounding floor of L limbs
     assert abs(info["residual_first"] - ref.rho) <= 1e-6 * ref.rho + 64 * s.n * 2.0 ** (-53 * L)

@@ -13,19 +13,27 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def test_learned_control_beats_plain_on_held_out_systems():
+    # all 50 held-out n=32 systems: fewer corrector stages than both plain
+    # controllers, and less wall time per path than the stronger one (the
+    # network runs on the device inside each corrector stage, so a stage
+    # costs about the same with and without it)
     from paper_1109_0545_amd import policy
 
-    say("learned vs plain on 10 held-out n=32 systems")
+    say("learned vs plain on the 50 held-out n=32 systems")
     r = policy.evaluate(os.path.join(ROOT, "tests", "golden", "family_heldout.json"),
-                        os.path.join(ROOT, "paper_1109_0545_amd", "policy_n32.npz"), limit=10)
+                        os.path.join(ROOT, "paper_1109_0545_amd", "policy_n32.npz"))
     s = r["summary"]
-    # judged against the stronger plain controller (quadratic predictor) and the secant one
+    assert s["systems"] == 50
     for base in ("plain_quadratic", "plain"):
         wins = sum(1 for row in r["rows"] if row["learned"]["corrections"] < row[base]["corrections"])
         assert s[f"{base}_fails"] == 0 and s[f"{base}_min_digits"] >= 28
         assert s["learned_mean_corrections"] < s[f"{base}_mean_corrections"]
-        assert wins >= 8, (base, r["rows"])
+        assert wins >= 40, (base, wins)
     assert s["learned_fails"] == 0 and s["learned_min_digits"] >= 28
+    say(f"  mean s/path: plain {s['plain_mean_seconds']:.4f}, quadratic {s['plain_quadratic_mean_seconds']:.4f}, "
+        f"learned {s['learned_mean_seconds']:.4f}; corrections {s['plain_mean_corrections']:.1f} / "
+        f"{s['plain_quadratic_mean_corrections']:.1f} / {s['learned_mean_corrections']:.1f}")
+    assert s["learned_mean_seconds"] < s["plain_quadratic_mean_seconds"]
 
 
 def test_learned_control_falls_back_when_the_network_is_wrong():
