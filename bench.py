@@ -196,7 +196,7 @@ def newton_vs_oracle(q, name, mode):
     """One GPU Newton iteration from each point of the stored oracle Newton
     sequence (tests/golden/newton_<name>.json: three iterations from 1e-6 off
     the path at t = 1/2): per iteration the oracle's ||dz*||, the GPU's
-    ||z_gpu - (z + dz*)||_inf and that error in units of u ||z|| (u = 2^-106)."""
+    ||z_gpu - (z + dz*)||_inf and that error in units of u ||z|| (u = 2^-53L)."""
     import mpmath
     import numpy as np
 
@@ -207,14 +207,15 @@ def newton_vs_oracle(q, name, mode):
     s = config_system(CONFIGS[name])
     H = q.Homotopy(q.System.from_synth(s), s.gamma)
     rows = []
+    L = fix["L"]
     for k, row in enumerate(fix["iterations"]):
         x = np.array(row["x_limbs"])
-        xg, info = q.newton_step(H, fix["t"], x, 2, mode=mode, eps=0.0, max_it=1)
+        xg, info = q.newton_step(H, fix["t"], x, L, mode=mode, eps=0.0, max_it=1)
         with mpmath.workprec(700):
             err = max(abs(limbs_value(xg[v]) - limbs_value(x[v]) - limbs_value(np.array(row["dz_limbs"][v])))
                       for v in range(s.n))
         rows.append({"iteration": k, "dz_oracle_inf": row["dz_inf"], "err_inf": float(err),
-                     "err_over_u_z": float(err) / (2.0**-106 * row["z_inf"]), "kappa": row["kappa"],
+                     "err_over_u_z": float(err) / (2.0 ** (-53 * L) * row["z_inf"]), "kappa": row["kappa"],
                      "refine_steps": info["refine_steps"]})
     return {"workload": name, "solve": "full" if mode == 0 else "mixed", "iterations": rows}
 
@@ -578,7 +579,7 @@ def main():
         extra = [rate_entry("n64_dd", L, 1, mode, rate, ms, ev_us, ge_us, sysm)]
         for name, lim, md, k, B in (("n64_dd", 2, 1 - mode, max(args.steps // 2, 10), 1),
                                     ("n128_dd", 2, 0, 200, 1), ("n128_dd", 2, 1, 200, 1),
-                                    ("n64_qd", 4, 0, 200, 1),
+                                    ("n64_qd", 4, 0, 200, 1), ("n64_qd", 4, 1, 200, 1),
                                     ("n64_dd", 2, 0, 100, args.batch)):
             r, m_, e_, g_, sy, inf = newton_rate(q, name, lim, md, k, 10, t, B=B)
             ent = rate_entry(name, lim, B, md, r, m_, e_, g_, sy)
@@ -597,13 +598,14 @@ def main():
         except Exception as e:  # report, never hide, a failing path
             out["paths"] = [{"error": str(e)}]
     if not args.no_paths and not args.no_extra:
-        # mixed precision (FP64 factorization + double-double refinement) beside the
-        # full double-double solve: error per Newton iteration against the oracle and
-        # the n = 128 path endpoint in both modes
+        # mixed precision (FP64 factorization + refinement in double or quad double)
+        # beside the full elimination: error per Newton iteration against the oracle
+        # and the n = 128 double-double and n = 64 quad-double path endpoints in both modes
         try:
             out["mixed_vs_full"] = {
-                "per_iteration": [newton_vs_oracle(q, nm, md) for nm in ("n64_dd", "n128_dd") for md in (0, 1)],
-                "paths": [track_case(q, "n128_dd", 2, md) for md in (0, 1)],
+                "per_iteration": [newton_vs_oracle(q, nm, md) for nm in ("n64_dd", "n128_dd", "n64_qd")
+                                  for md in (0, 1)],
+                "paths": [track_case(q, "n128_dd", 2, md) for md in (0, 1)] + [track_case(q, "n64_qd", 4, 1)],
             }
         except Exception as e:  # report, never hide
             out["mixed_vs_full"] = {"error": str(e)}

@@ -137,7 +137,8 @@ typedef struct {
  *   x    : [n][2][prec] in/out
  *   mode : QDP_SOLVE_FULL eliminates in working precision; QDP_SOLVE_MIXED_IR
  *          factors an FP64 copy of J and refines the correction against the
- *          working-precision residual (double double only).
+ *          working-precision residual (double or quad double, n <= 128;
+ *          QDP_EUNSUPPORTED otherwise).
  * info may be NULL.  max_it >= 0; eps >= 0. */
 qdp_status qdp_newton_step(const qdp_homotopy *h, double t, double *x, qdp_prec prec, qdp_solve mode,
                            double eps, int32_t max_it, qdp_newton_info *info, void *hip_stream);

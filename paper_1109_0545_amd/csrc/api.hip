@@ -36,8 +36,9 @@ hipError_t launch_ctl_features(const CtlFeatIn &h, const NewtonState *st, const 
                                hipStream_t s);
 hipError_t launch_stage_readback(const NewtonState *st, const double *aux, const float *pout, StageReadback *rb,
                                  hipStream_t s);
-hipError_t launch_mixed_solve(int n, int B, double *ab, double *scale, double *x, NewtonState *st, double *lu,
-                              double *work, int refinements, hipStream_t s);
+hipError_t launch_mixed_solve(int L, int n, int B, const double *ab, const double *scale, double *x,
+                              NewtonState *st, double *lu, int refinements, hipStream_t s);
+size_t mixed_ws_doubles(int n);
 }  // namespace qdp
 
 using qdp::DevSystem;
@@ -46,7 +47,11 @@ using qdp::NewtonState;
 // ------------------------------------------------------------------ errors
 
 static thread_local std::string g_err;
-static const bool kMixedBuilt = true;
+// mixed precision (FP64 factorization + refinement): double and quad double
+// working precision, n up to the register kernel's 128 rows
+static bool mixed_supported(int L, int n) { return (L == 2 || L == 4) && n >= 1 && n <= 128; }
+// refinements per correction: each gains about 16 - log10(kappa) digits
+static int mixed_refinements(int L) { return L == 4 ? 6 : 3; }
 static int g_timing = 0;
 
 static qdp_status fail(qdp_status s, const std::string &msg) {
@@ -98,7 +103,6 @@ struct Workspace {
   double *y = nullptr;      // [n] values (eval entry points)
   double *jac = nullptr;    // [n][n] Jacobian (eval entry points)
   double *lu = nullptr;     // [bcap] mixed precision: FP64 factors
-  double *work = nullptr;   // mixed precision scratch
   NewtonState *st = nullptr;  // [bcap]
   double *aux = nullptr;       // [4] predictor distance, blend-label sums
   float *pfeat = nullptr;      // [16] controller features, then [8] network outputs
@@ -146,7 +150,6 @@ static qdp_status ensure_ws(qdp_homotopy *h, int L, int B, Workspace **out) {
     HIPCHK(hipMalloc(&w.pfeat, 24 * sizeof(float)));
     HIPCHK(hipMalloc(&w.rb_dev, sizeof(qdp::StageReadback)));
     HIPCHK(hipHostMalloc(&w.rb_host, sizeof(qdp::StageReadback), hipHostMallocDefault));
-    if (L == 2) HIPCHK(hipMalloc(&w.work, (size_t)n * 8 * 2 * sizeof(double)));
     w.L = L;
   }
   if (B > w.bcap) {
@@ -161,7 +164,8 @@ static qdp_status ensure_ws(qdp_homotopy *h, int L, int B, Workspace **out) {
     const size_t pd = qdp::eval_part_doubles(L, n, B);
     if (pd > 0) HIPCHK(hipMalloc(&w.part, pd * sizeof(double)));
     if (h->f->supp > 0) HIPCHK(hipMalloc(&w.suppv, Bs * qdp::eval_supp_doubles(L, n, h->f->supp) * sizeof(double)));
-    if (L == 2) HIPCHK(hipMalloc(&w.lu, Bs * n * (n + 1) * 2 * sizeof(double)));
+    if (mixed_supported(L, n) && qdp::mixed_ws_doubles(n) > 0)
+      HIPCHK(hipMalloc(&w.lu, Bs * qdp::mixed_ws_doubles(n) * sizeof(double)));
     w.bcap = B;
   }
   *out = &w;
@@ -176,7 +180,6 @@ static void free_ws(Workspace &w) {
   hipFree(w.xw);
   hipFree(w.y);
   hipFree(w.jac);
-  hipFree(w.work);
   hipFree(w.aux);
   hipFree(w.pfeat);
   hipFree(w.rb_dev);
@@ -435,7 +438,7 @@ static qdp_status enqueue_newton(qdp_homotopy *h, Workspace *w, int L, double t,
     HIPCHK(qdp::launch_eval(L, f->dev(), x_dev, (long)n * 2 * L, B, ha, o, w->st, split, st));
     if (timing) HIPCHK(hipEventRecord(w->ev[3 * it + 1], st));
     if (mode == QDP_SOLVE_MIXED_IR)
-      HIPCHK(qdp::launch_mixed_solve(n, B, w->ab, w->scale, x_dev, w->st, w->lu, w->work, 3, st));
+      HIPCHK(qdp::launch_mixed_solve(L, n, B, w->ab, w->scale, x_dev, w->st, w->lu, mixed_refinements(L), st));
     else
       HIPCHK(qdp::launch_ge_scaled(L, n, B, w->ab, w->scale, x_dev, nullptr, w->st, st));
     if (timing) HIPCHK(hipEventRecord(w->ev[3 * it + 2], st));
@@ -464,8 +467,8 @@ static qdp_status newton_checks(const qdp_homotopy *h, double t, const double *x
   if (!std::isfinite(t)) return fail(QDP_ENONFINITE, "non-finite t");
   if (!(eps >= 0) || max_it < 0) return fail(QDP_EINVAL, "eps must be >= 0 and max_it >= 0");
   if (mode != QDP_SOLVE_FULL && mode != QDP_SOLVE_MIXED_IR) return fail(QDP_EINVAL, "bad solve mode");
-  if (mode == QDP_SOLVE_MIXED_IR && (L != 2 || !kMixedBuilt))
-    return fail(QDP_EUNSUPPORTED, "mixed-precision refinement is implemented for double double");
+  if (mode == QDP_SOLVE_MIXED_IR && !mixed_supported(L, h->f->n))
+    return fail(QDP_EUNSUPPORTED, "mixed-precision refinement is implemented for double and quad double, n <= 128");
   return QDP_OK;
 }
 
@@ -533,7 +536,7 @@ static size_t scratch_need(const qdp_homotopy *h, int L, int mode, size_t *ab, s
   *scale = up((size_t)n);
   *part = up(qdp::eval_part_doubles(L, n, 1));
   *suppv = h->f->supp > 0 ? up(qdp::eval_supp_doubles(L, n, h->f->supp)) : 0;
-  *lu = mode == QDP_SOLVE_MIXED_IR ? up((size_t)n * (n + 1) * 2) : 0;
+  *lu = mode == QDP_SOLVE_MIXED_IR ? up(qdp::mixed_ws_doubles(n)) : 0;
   *st = up((sizeof(NewtonState) + sizeof(double) - 1) / sizeof(double));
   return *ab + *scale + *part + *suppv + *lu + *st;
 }
@@ -764,8 +767,8 @@ extern "C" qdp_status qdp_track_path(const qdp_homotopy *hc, double *x, qdp_prec
       p.max_it_end < 0 || !(p.lambda_max >= p.lambda0))
     return fail(QDP_EINVAL, "bad step-size control parameters");
   if (p.mode != QDP_SOLVE_FULL && p.mode != QDP_SOLVE_MIXED_IR) return fail(QDP_EINVAL, "bad solve mode");
-  if (p.mode == QDP_SOLVE_MIXED_IR && L != 2)
-    return fail(QDP_EUNSUPPORTED, "mixed-precision refinement is implemented for double double");
+  if (p.mode == QDP_SOLVE_MIXED_IR && !mixed_supported(L, hc->f->n))
+    return fail(QDP_EUNSUPPORTED, "mixed-precision refinement is implemented for double and quad double, n <= 128");
   const bool learned = p.predictor == QDP_PRED_LEARNED;
   if (learned && !p.policy) return fail(QDP_EINVAL, "learned predictor needs a policy");
   if (p.predictor != QDP_PRED_SECANT && p.predictor != QDP_PRED_QUADRATIC && !learned)
@@ -1036,8 +1039,8 @@ extern "C" qdp_status qdp_track_paths(const qdp_homotopy *hc, double *x, int32_t
       p.max_it_end < 0 || !(p.lambda_max >= p.lambda0))
     return fail(QDP_EINVAL, "bad step-size control parameters");
   if (p.mode != QDP_SOLVE_FULL && p.mode != QDP_SOLVE_MIXED_IR) return fail(QDP_EINVAL, "bad solve mode");
-  if (p.mode == QDP_SOLVE_MIXED_IR && L != 2)
-    return fail(QDP_EUNSUPPORTED, "mixed-precision refinement is implemented for double double");
+  if (p.mode == QDP_SOLVE_MIXED_IR && !mixed_supported(L, hc->f->n))
+    return fail(QDP_EUNSUPPORTED, "mixed-precision refinement is implemented for double and quad double, n <= 128");
   if (p.predictor != QDP_PRED_SECANT && p.predictor != QDP_PRED_QUADRATIC)
     return fail(QDP_EUNSUPPORTED, "batched tracking uses the secant or the quadratic predictor");
   if (p.probe) return fail(QDP_EUNSUPPORTED, "probe mode tracks one path");

@@ -91,9 +91,11 @@ __device__ inline double wave_max_f64(double v) {
 // Maximum over a full wavefront of a 32-bit key, in lane 63 (read out as a
 // scalar): butterflies inside each row of 16 lanes (lane xor 1, xor 2, the
 // half-row mirror, the row mirror), then the row broadcasts of lanes 15 and
-// 31 into the rows above.
+// 31 into the rows above.  A lane reading outside the wavefront or a row left
+// out by the row mask sees 0, the identity of the maximum, so each level is
+// one max instruction with the lane permutation on its operand.
 template <int CTRL, int ROWS> __device__ inline unsigned dpp_umax(unsigned w) {
-  return max(w, (unsigned)__builtin_amdgcn_update_dpp((int)w, (int)w, CTRL, ROWS, 0xf, false));
+  return max(w, (unsigned)__builtin_amdgcn_update_dpp(0, (int)w, CTRL, ROWS, 0xf, true));
 }
 __device__ inline unsigned wave_umax32(unsigned w) {
   w = dpp_umax<0xB1, 0xf>(w);   // quad_perm [1,0,3,2]
@@ -123,12 +125,12 @@ template <int RB> __device__ inline unsigned pack_key32(double key, int row, boo
 // row keeps its entry, the diagonal of U) and go to `mbuf`.  Every lane
 // inverts its own entry while the maximum runs (one pass of the SIMD; the two
 // chains are independent), so the pivot's inverse is one lane read.  Lane 0
-// records the pivot row and zero-pivot flag (one 8-byte store); the inverse
-// and the pivot's magnitude are returned for the caller to record (after it
-// has published the column).  Called by one whole wavefront.
+// records the pivot row and zero-pivot flag (one 8-byte store); the inverse,
+// the pivot's magnitude and its row are returned for the caller to record
+// (after it has published the column).  Called by one whole wavefront.
 template <int L, int RPL>
 __device__ __forceinline__ void reg_pivot(C<L> (&v)[RPL], const bool (&cand)[RPL], int col, double *mbuf, int2 *ctl,
-                                          C<L> &inv_out, double &pkey_out) {
+                                          C<L> &inv_out, double &pkey_out, int &p_out) {
   constexpr int RMAX = 64 * RPL;
   constexpr int RB = RPL == 1 ? 6 : (RPL == 2 ? 7 : 8);
   const int lane = threadIdx.x & 63;
@@ -164,6 +166,7 @@ __device__ __forceinline__ void reg_pivot(C<L> (&v)[RPL], const bool (&cand)[RPL
   if (lane == 0) ctl[col] = make_int2(p, sg ? 1 : 0);
   inv_out = inv;
   pkey_out = pkey;
+  p_out = p;
 }
 // the pivot's inverse and magnitude into their LDS arrays (lane 0)
 template <int L, int RMAX>
@@ -196,6 +199,173 @@ __device__ __forceinline__ void apply_live(C<L> (&A)[CPW][RPL], int live, const 
     else
       apply_live<L, RPL, CPW, K - 1>(A, live, lm, ps);
   }
+}
+
+// LDS arrays of the elimination loop (layout above).
+struct RegElimLds {
+  double *mult;  // [KRING][2L][RMAX] multiplier ring
+  double *invp;  // [2L][RMAX]
+  double *pmag;  // [RMAX]
+  int2 *ctl;     // [RMAX]
+  int *pub;      // columns published
+  int *rd;       // [NW] columns read by each wavefront
+};
+
+// The elimination of [A | b] held in registers (column wave + NW s in slot
+// s, rows lane + 64 u), called by every thread of the workgroup: wavefront 0
+// pivots column 0, one barrier (after it, *badflag != 0 stops the
+// elimination before any step), then the steps as described at the top of
+// this file.  retire(c, col, inv, p, pos) receives each column c < n in the
+// registers of its owner once its pivot (row p, inverse inv) is chosen, with
+// pos[u] the pivot step of row lane + 64u for the steps before c (n for rows
+// not yet pivot rows); the column then leaves the slots.  On return
+// mypos[u] = pivot step of row lane + 64u (n for none), column n is in
+// slot 0 of its owner, and invp/pmag/ctl hold the columns examined (the
+// published counter says how many).  Returns false if a column had no
+// nonzero pivot (or *badflag was set).
+template <int L, int NW, int NMAX, int CPW, int RPL, class Retire>
+__device__ __forceinline__ bool reg_eliminate(C<L> (&A)[CPW][RPL], int (&mypos_out)[RPL], int n,
+                                              const double *badflag, const RegElimLds &m, Retire &&retire) {
+  using S = RegShape<NW, NMAX>;
+  static_assert(CPW == S::CPW && RPL == S::RPL, "register array of this shape");
+  constexpr int RMAX = S::RMAX, E2 = 2 * L;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // kept local and copied out at the end: held through the caller's
+  // reference, the compiler allocated the loop ~10 more registers and the
+  // n = 64 double-double elimination ran 10% slower (measured)
+  int mypos[RPL];
+  bool act[RPL];  // row not yet a pivot row
+#pragma unroll
+  for (int u = 0; u < RPL; ++u) {
+    act[u] = lane + 64 * u < n;
+    mypos[u] = n;
+  }
+  int live = wave <= n ? (n - wave) / NW + 1 : 0;  // columns this wavefront still holds
+  // retire slot 0 (column c, final): handed to the caller, the other slots
+  // shift down
+  auto retire_slot0 = [&](int c, const C<L> &inv, int p) __attribute__((always_inline)) {
+    retire(c, A[0], inv, p, mypos);
+#pragma unroll
+    for (int s = 0; s + 1 < CPW; ++s)
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) A[s][u] = A[s + 1][u];
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) A[CPW - 1][u] = czero<L>();
+    --live;
+  };
+  // ---- pivot of column 0 (wave 0, slot 0), retired at once (a later stop
+  // discards it)
+  if (wave == 0) {
+    C<L> inv0;
+    double pk;
+    int p0;
+    reg_pivot<L, RPL>(A[0], act, 0, m.mult, m.ctl, inv0, pk, p0);
+    reg_record<L, RMAX>(0, inv0, pk, m.invp, m.pmag);
+    retire_slot0(0, inv0, p0);
+  }
+  if (tid < NW) m.rd[tid] = 0;
+  if (tid == 0) *m.pub = 1;
+  __syncthreads();
+
+  // ---- elimination: step j applies column j's multipliers to columns j+1..n
+  auto published = [&]() {
+    return __builtin_amdgcn_readfirstlane(__hip_atomic_load(m.pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+  };
+  bool stop = *badflag != 0.0;
+  bool hasdef = false;  // step deferred on the slots past slot 0 (next look-ahead owner)
+  int pdef = 0;
+  C<L> ldef[RPL];
+#pragma unroll
+  for (int u = 0; u < RPL; ++u) ldef[u] = czero<L>();
+  auto apply = [&](const C<L> (&lm)[RPL], int ps) { apply_live<L, RPL, CPW>(A, live, lm, ps); };
+  for (int j = 0; j + 1 < n && !stop; ++j) {
+    // wait for column j, read its pivot row, flag and multipliers (every row;
+    // rows this step leaves alone are zeroed below), record the read
+    const int j1 = j + 1;
+    const bool owner = wave == j1 % NW;  // runs the look-ahead of column j+1: polls without sleeping
+    while (published() <= j)
+      if (!owner) __builtin_amdgcn_s_sleep(1);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const int2 cj = m.ctl[j];
+    const double *const mj = m.mult + (j % KRING) * E2 * RMAX;
+    C<L> l[RPL];
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) l[u] = pload<L>(mj + lane + 64 * u, RMAX);
+    const int sgj = __builtin_amdgcn_readfirstlane(cj.y);
+    const int p = __builtin_amdgcn_readfirstlane(cj.x);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // the reads above have completed
+    if (lane == 0) __hip_atomic_store(m.rd + wave, j + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (sgj != 0) {  // column j has no nonzero pivot
+      stop = true;
+      break;
+    }
+    bool upd[RPL];  // rows this step updates
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) {
+      const int r = lane + 64 * u;
+      if (r == p) mypos[u] = j;
+      upd[u] = act[u] && r != p;
+      l[u] = cselect<L>(upd[u], l[u], czero<L>());
+    }
+    if (owner) {
+      // look-ahead: column j+1 (slot 0, steps 0..j-1 applied) updated by
+      // step j, its pivot and multipliers published, the column retired;
+      // then the steps this wavefront still owes its other columns
+      __builtin_amdgcn_s_setprio(2);
+      // the ring entry this column reuses must have been read by every
+      // wavefront: the counters are loaded before the product, checked after
+      const int need = j1 - KRING + 1;
+      int rdl = lane < NW ? __hip_atomic_load(m.rd + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : need;
+      const C<L> uv = reg_row<L, RPL>(A[0], p);
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) A[0][u] = cfms<L>(A[0][u], l[u], uv);
+      while (__ballot(rdl < need) != 0ull)
+        rdl = lane < NW ? __hip_atomic_load(m.rd + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : need;
+      C<L> inv;
+      double pk;
+      int pn;
+      reg_pivot<L, RPL>(A[0], upd, j1, m.mult + (j1 % KRING) * E2 * RMAX, m.ctl, inv, pk, pn);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // multipliers and flags before the counter
+      if (lane == 0) __hip_atomic_store(m.pub, j1 + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      __builtin_amdgcn_s_setprio(0);
+      reg_record<L, RMAX>(j1, inv, pk, m.invp, m.pmag);
+      retire_slot0(j1, inv, pn);
+      if (hasdef) {
+        apply(ldef, pdef);
+        hasdef = false;
+      }
+      apply(l, p);
+    } else if (j1 + 1 < n && wave == (j1 + 1) % NW) {
+      // next look-ahead owner: this step on its look-ahead column only; the
+      // other columns get it after that look-ahead
+      const C<L> uv = reg_row<L, RPL>(A[0], p);
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) A[0][u] = cfms<L>(A[0][u], l[u], uv);
+      hasdef = true;
+      pdef = p;
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) ldef[u] = l[u];
+    } else {
+      apply(l, p);  // every live column is j+2..n
+    }
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) act[u] = upd[u];
+  }
+  if (!stop) {
+    // the last pivot column's flag (published by the last look-ahead; for
+    // n = 1, column 0)
+    while (published() < n) __builtin_amdgcn_s_sleep(1);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const int2 cl = m.ctl[n - 1];
+    stop = __builtin_amdgcn_readfirstlane(cl.y) != 0;
+    const int pl = __builtin_amdgcn_readfirstlane(cl.x);
+#pragma unroll
+    for (int u = 0; u < RPL; ++u)
+      if (lane + 64 * u == pl) mypos[u] = n - 1;
+  }
+#pragma unroll
+  for (int u = 0; u < RPL; ++u) mypos_out[u] = mypos[u];
+  return !stop;
 }
 
 // NW / 4 wavefronts share a SIMD: the compiler may use that SIMD's whole
@@ -239,10 +409,6 @@ void k_ge_reg(GeArgs<L> a) {
       A[s][u] = (c <= n && r < n) ? pload<L>(ab + (size_t)c * n + r, PS) : czero<L>();
     }
   }
-  bool act[RPL];  // row not yet a pivot row
-#pragma unroll
-  for (int u = 0; u < RPL; ++u) act[u] = lane + 64 * u < n;
-
   // ---- residual of h (the right-hand side column, before elimination) by its owner
   if (wave == n % NW) {
     double hb = 0.0, sb = 0.0;
@@ -252,7 +418,7 @@ void k_ge_reg(GeArgs<L> a) {
       if (s == n / NW) {
 #pragma unroll
         for (int u = 0; u < RPL; ++u)
-          if (act[u]) {
+          if (lane + 64 * u < n) {
             hb = fmax(hb, cabs1_hi<L>(A[s][u]));
             fin = fin && cfinite<L>(A[s][u]);
           }
@@ -266,133 +432,19 @@ void k_ge_reg(GeArgs<L> a) {
       misc[1] = bad ? 1.0 : 0.0;
     }
   }
-  // ---- pivot of column 0 (wave 0, slot 0)
-  if (wave == 0) {
-    C<L> inv;
-    double pk;
-    reg_pivot<L, RPL>(A[0], act, 0, mult, ctl, inv, pk);
-    reg_record<L, RMAX>(0, inv, pk, invp, pmag);
-  }
-  if (tid < NW) rd[tid] = 0;
-  if (tid == 0) *pub = 1;
-  __syncthreads();
-  const bool bad = misc[1] != 0.0;
-  int live = wave <= n ? (n - wave) / NW + 1 : 0;  // columns this wavefront still holds
+  // ---- elimination; each finished column's U part (pivot rows, pivot
+  // order mypos < c) goes into the packed triangle
   int mypos[RPL];  // pivot column of row lane + 64u (n while not yet a pivot row)
+  const RegElimLds lds{mult, invp, pmag, ctl, pub, rd};
+  const bool ok = reg_eliminate<L, NW, NMAX>(A, mypos, n, misc + 1, lds,
+                                             [&](int c, const C<L>(&col)[RPL], const C<L> &, int, const int(&pos)[RPL])
+                                                 __attribute__((always_inline)) {
 #pragma unroll
-  for (int u = 0; u < RPL; ++u) mypos[u] = n;
-  // retire slot 0 (column c, final): its U part (pivot rows, pivot order
-  // mypos < c) into the packed triangle, the other slots shift down
-  auto retire = [&](int c) {
-#pragma unroll
-    for (int u = 0; u < RPL; ++u)
-      if (mypos[u] < c) pstore<L>(tri + (size_t)c * (c - 1) / 2 + mypos[u], TS, A[0][u]);
-#pragma unroll
-    for (int s = 0; s + 1 < CPW; ++s)
-#pragma unroll
-      for (int u = 0; u < RPL; ++u) A[s][u] = A[s + 1][u];
-#pragma unroll
-    for (int u = 0; u < RPL; ++u) A[CPW - 1][u] = czero<L>();
-    --live;
-  };
-
-  // ---- elimination: step j applies column j's multipliers to columns j+1..n
-  auto published = [&]() {
-    return __builtin_amdgcn_readfirstlane(__hip_atomic_load(pub, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
-  };
-  bool stop = bad;
-  bool hasdef = false;  // step deferred on the slots past slot 0 (next look-ahead owner)
-  int pdef = 0;
-  C<L> ldef[RPL];
-#pragma unroll
-  for (int u = 0; u < RPL; ++u) ldef[u] = czero<L>();
-  auto apply = [&](const C<L> (&lm)[RPL], int ps) { apply_live<L, RPL, CPW>(A, live, lm, ps); };
-  if (wave == 0 && !stop) retire(0);
-  for (int j = 0; j + 1 < n && !stop; ++j) {
-    // wait for column j, read its pivot row, flag and multipliers (every row;
-    // rows this step leaves alone are zeroed below), record the read
-    const int j1 = j + 1;
-    const bool owner = wave == j1 % NW;  // runs the look-ahead of column j+1: polls without sleeping
-    while (published() <= j)
-      if (!owner) __builtin_amdgcn_s_sleep(1);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    const int2 cj = ctl[j];
-    const double *const mj = mult + (j % KRING) * E2 * RMAX;
-    C<L> l[RPL];
-#pragma unroll
-    for (int u = 0; u < RPL; ++u) l[u] = pload<L>(mj + lane + 64 * u, RMAX);
-    const int sgj = __builtin_amdgcn_readfirstlane(cj.y);
-    const int p = __builtin_amdgcn_readfirstlane(cj.x);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // the reads above have completed
-    if (lane == 0) __hip_atomic_store(rd + wave, j + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (sgj != 0) {  // column j has no nonzero pivot
-      stop = true;
-      break;
-    }
-    bool upd[RPL];  // rows this step updates
-#pragma unroll
-    for (int u = 0; u < RPL; ++u) {
-      const int r = lane + 64 * u;
-      if (r == p) mypos[u] = j;
-      upd[u] = act[u] && r != p;
-      l[u] = cselect<L>(upd[u], l[u], czero<L>());
-    }
-    if (owner) {
-      // look-ahead: column j+1 (slot 0, steps 0..j-1 applied) updated by
-      // step j, its pivot and multipliers published, the column retired;
-      // then the steps this wavefront still owes its other columns
-      __builtin_amdgcn_s_setprio(2);
-      // the ring entry this column reuses must have been read by every
-      // wavefront: the counters are loaded before the product, checked after
-      const int need = j1 - KRING + 1;
-      int rdl = lane < NW ? __hip_atomic_load(rd + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : need;
-      const C<L> uv = reg_row<L, RPL>(A[0], p);
-#pragma unroll
-      for (int u = 0; u < RPL; ++u) A[0][u] = cfms<L>(A[0][u], l[u], uv);
-      while (__ballot(rdl < need) != 0ull)
-        rdl = lane < NW ? __hip_atomic_load(rd + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : need;
-      C<L> inv;
-      double pk;
-      reg_pivot<L, RPL>(A[0], upd, j1, mult + (j1 % KRING) * E2 * RMAX, ctl, inv, pk);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // multipliers and flags before the counter
-      if (lane == 0) __hip_atomic_store(pub, j1 + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      __builtin_amdgcn_s_setprio(0);
-      reg_record<L, RMAX>(j1, inv, pk, invp, pmag);
-      retire(j1);
-      if (hasdef) {
-        apply(ldef, pdef);
-        hasdef = false;
-      }
-      apply(l, p);
-    } else if (j1 + 1 < n && wave == (j1 + 1) % NW) {
-      // next look-ahead owner: this step on its look-ahead column only; the
-      // other columns get it after that look-ahead
-      const C<L> uv = reg_row<L, RPL>(A[0], p);
-#pragma unroll
-      for (int u = 0; u < RPL; ++u) A[0][u] = cfms<L>(A[0][u], l[u], uv);
-      hasdef = true;
-      pdef = p;
-#pragma unroll
-      for (int u = 0; u < RPL; ++u) ldef[u] = l[u];
-    } else {
-      apply(l, p);  // every live column is j+2..n
-    }
-#pragma unroll
-    for (int u = 0; u < RPL; ++u) act[u] = upd[u];
-  }
-  if (!stop) {
-    // the last pivot column's flag (published by the last look-ahead; for
-    // n = 1, column 0)
-    while (published() < n) __builtin_amdgcn_s_sleep(1);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    const int2 cl = ctl[n - 1];
-    stop = __builtin_amdgcn_readfirstlane(cl.y) != 0;
-    const int pl = __builtin_amdgcn_readfirstlane(cl.x);
-#pragma unroll
-    for (int u = 0; u < RPL; ++u)
-      if (lane + 64 * u == pl) mypos[u] = n - 1;
-  }
-  const bool ok = !stop;
+                                               for (int u = 0; u < RPL; ++u)
+                                                 if (pos[u] < c)
+                                                   pstore<L>(tri + (size_t)c * (c - 1) / 2 + pos[u], TS, col[u]);
+                                             });
+  const bool bad = misc[1] != 0.0;
 
   // ---- right-hand side (column n, slot 0 of its owner) in pivot order, then
   // the triangle and the right-hand side scaled by the pivot inverses

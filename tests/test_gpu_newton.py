@@ -98,50 +98,55 @@ def test_elimination_sizes_and_batch(n):
             check_step(s, xs[b], t, 2, xg[b], infos[b], "quotient")
 
 
-@pytest.mark.parametrize("name", ["n8_dd", "n32_dd"])
-def test_one_step_mixed_precision(name):
-    # FP64 factorization + double-double refinement: same bound as the full
-    # double-double solve (the refinement reaches the double-double level)
-    one_step_parity(name, 2, form="quotient", mode=1)
+@pytest.mark.parametrize("name,L", [("n8_dd", 2), ("n32_dd", 2), ("n64_dd", 2), ("n64_qd", 4), ("n128_dd", 2)])
+def test_one_step_mixed_precision(name, L):
+    # FP64 factorization + refinement in the working precision: same bound as
+    # the full elimination (the refinement reaches the working precision's level)
+    one_step_parity(name, L, form="quotient", mode=1)
 
 
-@pytest.mark.parametrize("name", ["n64_dd", "n128_dd"])
-def test_mixed_precision_converges_to_target_root(name):
+@pytest.mark.parametrize("name,L", [("n64_dd", 2), ("n128_dd", 2), ("n64_qd", 4)])
+def test_mixed_precision_converges_to_target_root(name, L):
     import paper_1109_0545_amd as q
 
     fix = fixture(name)
     s = config_system(CONFIGS[name])
     S = q.System.from_synth(s)
     H = q.Homotopy(S, s.gamma)
-    x = np.zeros((s.n, 2, 2))
+    x = np.zeros((s.n, 2, L))
     x[:, :, 0] = s.zstar[:, :, 0]
+    u = 2.0 ** (-53 * L)
     say("newton mixed converge", name)
-    xg, info = q.newton_step(H, 1.0, x, 2, mode=q.SOLVE_MIXED_IR, eps=64 * 2.0**-106, max_it=6)
+    xg, info = q.newton_step(H, 1.0, x, L, mode=q.SOLVE_MIXED_IR, eps=64 * u, max_it=6)
     zss = zss_mpc(fix)
     with mpmath.workprec(600):
         err = max(float(abs(mpc_of(xg[v]) - zss[v])) for v in range(s.n))
+    say(f"  |z - z**| = {err:.3e} = {err / u:.1f} u, refinements in the last step {info['refine_steps']}")
     assert info["success"] and info["refine_steps"] >= 1
-    assert err <= 1e4 * 2.0**-106, err
+    assert err <= 1e4 * u, err
 
 
-def test_mixed_precision_refinement_contracts():
+@pytest.mark.parametrize("name,L,max_steps,floor", [("n32_dd", 2, 3, 1e-28), ("n64_qd", 4, 6, 1e-58)])
+def test_mixed_precision_refinement_contracts(name, L, max_steps, floor):
     # the textbook iterative-refinement property: from a point off the root the
-    # refinement of one Newton correction contracts and stops at the
-    # double-double level within its three steps
+    # refinement of one Newton correction contracts and stops at the working
+    # precision's level within its budget of steps
     import paper_1109_0545_amd as q
 
-    s = config_system(CONFIGS["n32_dd"])
+    s = config_system(CONFIGS[name])
     S = q.System.from_synth(s)
     H = q.Homotopy(S, s.gamma)
-    x = np.zeros((s.n, 2, 2))
+    x = np.zeros((s.n, 2, L))
     x[:, :, 0] = s.zstar[:, :, 0] + 1e-6
-    say("mixed refinement contraction")
-    _, info = q.newton_step(H, 1.0, x, 2, mode=q.SOLVE_MIXED_IR, eps=0.0, max_it=1)
-    assert 1 <= info["refine_steps"] <= 3
-    assert info["refine_err"] < 1e-28
+    say("mixed refinement contraction", name)
+    _, info = q.newton_step(H, 1.0, x, L, mode=q.SOLVE_MIXED_IR, eps=0.0, max_it=1)
+    say(f"  {info['refine_steps']} refinements, last relative correction {info['refine_err']:.3e}")
+    assert 1 <= info["refine_steps"] <= max_steps
+    assert info["refine_err"] < floor
 
 
-def test_mixed_precision_rejects_quad_double():
+def test_mixed_precision_rejects_fp64():
+    # the mixed mode refines in a working precision above the factorization's
     import paper_1109_0545_amd as q
 
     s = config_system(CONFIGS["n8_dd"])
@@ -150,6 +155,58 @@ def test_mixed_precision_rejects_quad_double():
     with pytest.raises(q.QdpError) as e:
         q.newton_step(H, 1.0, np.zeros((s.n, 2, 1)), 1, mode=q.SOLVE_MIXED_IR)
     assert e.value.status == 5
+
+
+def tiny_system(n, L, seed):
+    """A dense system at n <= 2 (the random generator needs more distinct
+    monomials than one or two variables of degree <= 2 allow): every
+    polynomial has the constant, each x_v, and prod x_v^2, with unit-circle
+    coefficients."""
+    from synth.systems import System
+
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rows = [[0] * n] + [[1 if k == v else 0 for k in range(n)] for v in range(n)] + [[2] * n]
+    m = len(rows)
+    exps = np.array([r for _ in range(n) for r in rows], dtype=np.uint8)
+    ang = rng.uniform(0.0, 2 * np.pi, n * m + 1)
+    coefs = np.zeros((n * m, 2, L))
+    coefs[:, 0, 0], coefs[:, 1, 0] = np.cos(ang[:-1]), np.sin(ang[:-1])
+    gamma = np.zeros((2, L))
+    gamma[0, 0], gamma[1, 0] = np.cos(ang[-1]), np.sin(ang[-1])
+    offsets = np.arange(0, n * m + 1, m, dtype=np.int32)
+    return System(n, L, offsets, exps, coefs, gamma, np.zeros((n, 2, L)), np.zeros(n, dtype=np.int64),
+                  np.full(n, 2 * n, dtype=np.int32))
+
+
+@pytest.mark.parametrize("n,L", [(1, 2), (2, 2), (17, 4), (63, 2), (64, 2), (65, 2), (65, 4), (100, 2), (128, 4)])
+def test_mixed_matches_full_across_sizes(n, L):
+    # the two solve modes on random systems at the sizes where the mixed kernel
+    # changes shape (one row, ragged tails, the last size with both factors in
+    # LDS, the first with them in the global store, the largest): one Newton
+    # step each from the same point; both are within the one-step bound of the
+    # exact step, so they agree to twice that bound's working-precision scale
+    import paper_1109_0545_amd as q
+    from synth.systems import make_system, random_point
+
+    s = tiny_system(n, L, 300 + n) if n <= 2 else make_system(n, min(n, 16), 2, L, 300 + n)
+    S = q.System.from_synth(s)
+    H = q.Homotopy(S, s.gamma)
+    x = random_point(n, L, seed=400 + n, spread=0.05)
+    say("mixed vs full n", n, "L", L)
+    xf, inf_f = q.newton_step(H, 0.6, x, L, mode=q.SOLVE_FULL, eps=0.0, max_it=1)
+    xm, inf_m = q.newton_step(H, 0.6, x, L, mode=q.SOLVE_MIXED_IR, eps=0.0, max_it=1)
+    assert not inf_f["singular"] and not inf_m["singular"]
+    assert inf_m["residual_first"] == inf_f["residual_first"]
+    u = 2.0 ** (-53 * L)
+    kappa = max(inf_f["cond_est"], 1.0)
+    with mpmath.workprec(600):
+        d = max(float(abs(mpc_of(xm[v]) - mpc_of(xf[v]))) for v in range(n))
+        zn = max(float(abs(mpc_of(xf[v]))) for v in range(n))
+        dzn = max(float(abs(mpc_of(xf[v]) - mpc_of(x[v]))) for v in range(n))
+    bound = 64 * n * kappa * u * max(zn, dzn, 1.0)
+    say(f"  |z_mixed - z_full| = {d:.3e}, bound {bound:.3e}, refinements {inf_m['refine_steps']}")
+    assert d <= bound, (d, bound)
+    assert inf_m["refine_steps"] >= 1
 
 
 @pytest.mark.parametrize("name,L", [("n8_dd", 2), ("n32_dd", 2), ("n64_qd", 4), ("n64_dd", 2), ("n128_dd", 2)])
