@@ -14,7 +14,9 @@
 //   2. dz = (LU)^-1 P fl64(b);
 //   3. up to R times: r = b - J dz in the working precision (J and b the full
 //      evaluation), c = (LU)^-1 P fl64(r) with the FP64 factors, dz += c; stop
-//      once ||c|| <= 2^(-52 L) ||dz||;
+//      once rho_k = ||c_k|| / ||dz|| <= 2^(-52 L), or once the next correction,
+//      predicted as rho_k times the observed contraction rho_k / rho_(k-1),
+//      falls below it (the error left in dz is about that next correction);
 //   4. z += dz.
 // With kappa(J) u64 << 1 each refinement gains about -log10(kappa u64)
 // digits, up to the working precision's level.  The residual, the pivot
@@ -52,11 +54,11 @@ struct MixedArgs {
 };
 
 // column chunks of the residual: as many as the workgroup has rows of threads
-// for, at most 16 (8 in quad double, to bound the LDS of the partial sums)
+// for, at most 16; their partial sums (2L n chunks doubles) fit the region
+// they share (2 n^2 doubles up to n = 64, a staged triangle beyond)
 __host__ __device__ inline int mixed_chunks(int NT, int n, int L) {
   const int c = NT / n;
-  const int cap = L == 4 ? 8 : 16;
-  return c < 1 ? 1 : (c > cap ? cap : c);
+  return c < 1 ? 1 : (c > 16 ? 16 : c);
 }
 
 // LDS layout (double offsets; the int arrays at `ints`):
@@ -153,11 +155,14 @@ __device__ __forceinline__ void lower_solve(C<1> (&y)[RPL], const double *lp, in
     for (int u = 0; u < RPL; ++u) y[u] = cfms<1>(y[u], b[u], yc);  // zero up to row c
     colL(c + PF, b);
   };
-  for (int c0 = 0; c0 + 1 < n; c0 += PF) {
+  int c0 = 0;
+  for (; c0 + PF < n; c0 += PF) {  // full groups: steps c0..c0+PF-1 all < n-1
 #pragma unroll
-    for (int k = 0; k < PF; ++k)
-      if (c0 + k + 1 < n) step(c0 + k, buf[k]);  // wave-uniform
+    for (int k = 0; k < PF; ++k) step(c0 + k, buf[k]);
   }
+#pragma unroll
+  for (int k = 0; k < PF; ++k)
+    if (c0 + k + 1 < n) step(c0 + k, buf[k]);  // wave-uniform
 }
 // y <- U''^-1 y with U' (y_i -= U'(i,c) y_c for i < c, c = n-1..1); the
 // division by U(c,c) is left to the caller
@@ -188,11 +193,14 @@ __device__ __forceinline__ void upper_solve(C<1> (&y)[RPL], const double *up, in
     colU(c - PF, b);
   };
   // step m handles column c = n - 1 - m
-  for (int m0 = 0; m0 + 1 < n; m0 += PF) {
+  int m0 = 0;
+  for (; m0 + PF < n; m0 += PF) {  // full groups: columns n-1-m0..n-PF-m0, all > 0
 #pragma unroll
-    for (int k = 0; k < PF; ++k)
-      if (m0 + k + 1 < n) step(n - 1 - m0 - k, buf[k]);  // wave-uniform
+    for (int k = 0; k < PF; ++k) step(n - 1 - m0 - k, buf[k]);
   }
+#pragma unroll
+  for (int k = 0; k < PF; ++k)
+    if (m0 + k + 1 < n) step(n - 1 - m0 - k, buf[k]);  // wave-uniform
 }
 
 template <int L, int NW, int NMAX>
@@ -385,7 +393,7 @@ void k_mixed(MixedArgs a) {
   const int cw = (n + nch - 1) / nch;
   const double eps_r = L == 2 ? 0x1p-104 : 0x1p-208;
   int steps = 0;
-  double rel = 0.0;
+  double rel = 0.0, rel_prev = 0.0;
   for (int it = 0; ok && it < a.max_refine; ++it) {
     __syncthreads();  // dz complete; the staged triangle read
     {
@@ -472,7 +480,9 @@ void k_mixed(MixedArgs a) {
     __syncthreads();
     ++steps;
     rel = red[1] > 0.0 ? red[0] / red[1] : 0.0;
-    if (rel <= eps_r) break;  // uniform: every thread reads the same values
+    // uniform: every thread reads the same values
+    if (rel <= eps_r || (steps >= 2 && rel * rel <= eps_r * rel_prev)) break;
+    rel_prev = rel;
   }
   __syncthreads();
 
