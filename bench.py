@@ -493,6 +493,9 @@ def main():
                     help="run only the speedup / quality-up study over compute units and print it")
     ap.add_argument("--profile-common", action="store_true",
                     help="run only the common-support line (--steps Newton iterations) and print it")
+    ap.add_argument("--profile-line", choices=["n64_dd", "n128_dd", "n64_qd"],
+                    help="run only this one-path Newton line (--mode, --steps iterations) and print its rates "
+                         "(for profiling the mixed-precision and quad-double kernels)")
     ap.add_argument("--profile-batch", action="store_true",
                     help="run only the batched Newton line (n=64 double double, --batch points per launch, "
                          "--steps iterations) and print its rates (for profiling the batched evaluation)")
@@ -518,6 +521,13 @@ def main():
     L = 2
     t = 0.5
     mode = q.SOLVE_FULL if args.mode == "full" else q.SOLVE_MIXED_IR
+    if args.profile_line:
+        lim = 4 if args.profile_line.endswith("qd") else 2
+        r, m_, e_, g_, sy, inf = newton_rate(q, args.profile_line, lim, mode, args.steps, args.warmup, t)
+        ent = rate_entry(args.profile_line, lim, 1, mode, r, m_, e_, g_, sy)
+        ent["refine_steps"] = inf["refine_steps"]
+        print(json.dumps(ent))
+        return
     if args.cu_study:
         print(json.dumps(cu_study(q, B=args.batch)))
         return
