@@ -14,8 +14,8 @@ hipError_t launch_eval_qd(const DevSystem &, const double *, long, int, const Ho
 // run, i.e. for batches of B < 512 / n points: scratch for at most that many.
 size_t eval_part_doubles(int L, int n, int B) {
   const int bs = B < 511 / n ? B : 511 / n;
-  // records of (n+1) complex partial sums and a scale sum
-  return (size_t)bs * n * kMaxEvalParts * ((size_t)(n + 1) * 2 * L + 1);
+  // records of (n+1) complex partial sums and a scale sum, then the start-system powers
+  return (size_t)bs * n * (kMaxEvalParts * ((size_t)(n + 1) * 2 * L + 1) + 4 * (size_t)L);
 }
 
 

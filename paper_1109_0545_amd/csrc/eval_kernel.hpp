@@ -47,6 +47,11 @@ template <int L> struct EvalArgs {
 // doubles of one partial-row record: n+1 complex values, then the scale sum
 __host__ __device__ inline size_t part_record(int n, int L) { return (size_t)(n + 1) * 2 * L + 1; }
 __host__ __device__ inline size_t part_scale_at(int n, int L) { return (size_t)(n + 1) * 2 * L; }
+// doubles per point of a split evaluation with P parts: the n x P partial
+// records, then the start-system powers (x_i^(d_i - 1), x_i^(d_i)) of every row
+__host__ __device__ inline size_t part_point_doubles(int n, int L, int P) {
+  return (size_t)n * P * part_record(n, L) + (size_t)4 * L * n;
+}
 
 // Start-system powers of row i: pd1 = x_i^(d-1), pd = x_i^d by binary
 // powering in working precision (relative error about d units of the last
@@ -108,27 +113,22 @@ __device__ void eval_finish(const EvalArgs<L> &a, int b, int i, int col, C<L> s,
 }
 
 // Second stage of a split evaluation: row i of point b is the sum of its P
-// partial rows in part order, then blended and stored.  Thread 0 forms the
-// start-system powers first (a short chain on an otherwise idle unit).
+// partial rows in part order, then blended (with the start-system powers the
+// first stage's extra workgroup formed) and stored.
 template <int L>
 __global__ __launch_bounds__(256) void k_eval_sum(EvalArgs<L> a) {
   const int b = blockIdx.y, i = blockIdx.x;
   if (a.gate && !a.gate[b].active) return;
   const int n = a.s.n;
   const size_t rec = part_record(n, L);
-  const double *rows = a.part + ((size_t)b * n + i) * a.P * rec;
-  __shared__ double powbuf[4 * L];
-  if (threadIdx.x == 0 && a.h.homotopy) {
-    C<L> q1, q;
-    start_powers<L>(a.x + (size_t)b * a.bx + (size_t)i * 2 * L, a.s.deg[i], q1, q);
-    cstore<L>(powbuf, q1);
-    cstore<L>(powbuf + 2 * L, q);
-  }
-  __syncthreads();
+  const double *pt = a.part + (size_t)b * part_point_doubles(n, L, a.P);
+  const double *rows = pt + (size_t)i * a.P * rec;
+  // the start-system powers, formed by k_eval's extra workgroup
   C<L> pd1 = czero<L>(), pd = cone<L>();
   if (a.h.homotopy) {
-    pd1 = cload<L>(powbuf);
-    pd = cload<L>(powbuf + 2 * L);
+    const double *pw = pt + (size_t)n * a.P * rec + (size_t)i * 4 * L;
+    pd1 = cload<L>(pw);
+    pd = cload<L>(pw + 2 * L);
   }
   for (int col = threadIdx.x; col <= n; col += 256) {
     // every load first (the parts are independent), then the fixed-order sum
@@ -222,9 +222,13 @@ __device__ __forceinline__ C<L> monomial_walk(const int (&ex)[CH], const C<L> &c
 // batched case) thread 0 forms the start-system powers in the workgroup's
 // tail: a chain of dependent products that the other workgroups sharing the
 // compute unit cover (an extra wavefront for it cost a workgroup slot per CU:
-// measured 33% slower at 256 points); split evaluations form them in
-// k_eval_sum.  The register budget is that of NT + 64 threads (five
-// wavefronts), which keeps three four-wavefront workgroups per CU.
+// measured 33% slower at 256 points); a split evaluation (few points, many
+// parts per polynomial) gets one extra workgroup per point that forms them for
+// every row while the parts run (in k_eval_sum they were a serial tail; one
+// evaluation at n = 64 measured 22.3 -> 18.8 us in double double, 89.5 -> 79.7
+// us in quad double).  The register budget
+// is that of NT + 64 threads (five wavefronts), which keeps three
+// four-wavefront workgroups per CU.
 template <int L, int CH, int LM, int NT>
 __global__ __launch_bounds__(NT + 64) void k_eval(EvalArgs<L> a) {
   constexpr int G = 64 / LM;  // monomials per wavefront at a time
@@ -233,9 +237,24 @@ __global__ __launch_bounds__(NT + 64) void k_eval(EvalArgs<L> a) {
   const int b = blockIdx.y;
   if (a.gate && !a.gate[b].active) return;
   const double *x = a.x + (size_t)b * a.bx;
+  const int n = a.s.n;
+  if (a.P > 1 && (int)blockIdx.x == n * a.P) {
+    // split evaluation: the extra workgroup of a point forms the start-system
+    // powers of every row (a chain of ~2 log2 d products per row) while the
+    // parts run, for k_eval_sum
+    if (a.h.homotopy) {
+      double *pw = a.part + (size_t)b * part_point_doubles(n, L, a.P) + (size_t)n * a.P * part_record(n, L);
+      for (int r = threadIdx.x; r < n; r += NT) {
+        C<L> q1, q;
+        start_powers<L>(x + (size_t)r * 2 * L, a.s.deg[r], q1, q);
+        cstore<L>(pw + (size_t)r * 4 * L, q1);
+        cstore<L>(pw + (size_t)r * 4 * L + 2 * L, q);
+      }
+    }
+    return;
+  }
 
   extern __shared__ double smem[];
-  const int n = a.s.n;
   const int E1 = a.s.emax + 1;
   const int nv = table_stride(n);
   const size_t tps = (size_t)E1 * nv;  // plane size of one table
@@ -384,7 +403,7 @@ __global__ __launch_bounds__(NT + 64) void k_eval(EvalArgs<L> a) {
     return;
   }
   const size_t rec = part_record(n, L);
-  double *mine = a.part + (((size_t)b * n + i) * a.P + part) * rec;
+  double *mine = a.part + (size_t)b * part_point_doubles(n, L, a.P) + ((size_t)i * a.P + part) * rec;
   for (int col = tid; col <= n; col += NT) {
     C<L> s = pload<L>(red + col, rps);
     for (int w = 1; w < W; ++w) s = cadd<L>(s, pload<L>(red + (size_t)w * rn + col, rps));
@@ -416,7 +435,7 @@ inline int next_pow2(int v) {
 
 template <int L, int CH, int NT>
 hipError_t launch_eval_lm(int LM, const EvalArgs<L> &a, int B, hipStream_t st) {
-  dim3 grid(a.s.n * a.P, B), block(NT);
+  dim3 grid(a.s.n * a.P + (a.P > 1 ? 1 : 0), B), block(NT);  // + the start-power workgroup of a split
   const size_t lds = eval_lds_bytes_nt(L, a.s, NT);
   if (lds > 64 * 1024) {
     hipError_t e = hipSuccess;

@@ -277,7 +277,9 @@ __device__ __forceinline__ bool reg_eliminate(C<L> (&A)[CPW][RPL], int (&mypos_o
   C<L> ldef[RPL];
 #pragma unroll
   for (int u = 0; u < RPL; ++u) ldef[u] = czero<L>();
-  auto apply = [&](const C<L> (&lm)[RPL], int ps) { apply_live<L, RPL, CPW>(A, live, lm, ps); };
+  auto apply = [&](const C<L> (&lm)[RPL], int ps) __attribute__((always_inline)) {
+    apply_live<L, RPL, CPW>(A, live, lm, ps);
+  };
   for (int j = 0; j + 1 < n && !stop; ++j) {
     // wait for column j, read its pivot row, flag and multipliers (every row;
     // rows this step leaves alone are zeroed below), record the read
