@@ -53,6 +53,7 @@ typedef enum {
 
 typedef enum { QDP_SOLVE_FULL = 0, QDP_SOLVE_MIXED_IR = 1 } qdp_solve;
 typedef enum { QDP_PRED_SECANT = 0, QDP_PRED_LEARNED = 1, QDP_PRED_QUADRATIC = 2 } qdp_pred;
+typedef enum { QDP_ELIM_AUTO = 0, QDP_ELIM_POINT = 1, QDP_ELIM_COLUMNS = 2 } qdp_elim;
 
 typedef struct qdp_system qdp_system;
 typedef struct qdp_homotopy qdp_homotopy;
@@ -148,7 +149,8 @@ qdp_status qdp_newton_step_dev(const qdp_homotopy *h, double t, double *x, qdp_p
 /* For callers that cannot allocate device memory (code under stream capture,
  * tight serving loops, harnesses that forbid allocation): qdp_newton_step_dev
  * with its whole workspace ([A | -h], scales, state, split-evaluation partial
- * rows, common-support partials, FP64 factors of one point) in a static device
+ * rows, common-support partials, FP64 factors or the column-parallel
+ * elimination's multipliers and flags, of one point) in a static device
  * array of 8 MiB per GPU instead of the homotopy's allocated workspace; it calls
  * no allocating routine.  Results are bit for bit those of qdp_newton_step_dev.
  *   x        : [n][2][prec] device memory, in/out
@@ -337,6 +339,24 @@ qdp_status qdp_track_paths(const qdp_homotopy *h, double *x, int32_t B, qdp_prec
  *        tie, the lowest index wins; -1 when every key is zero or NaN). */
 qdp_status qdp_arith_batch(int32_t op, qdp_prec prec, int64_t count, const double *a, const double *b,
                            const double *c, double *out, void *hip_stream);
+
+/* How the working-precision elimination of Section 4 (GE with partial
+ * pivoting and Back_Subs) is laid out on the GPU, process-wide, for
+ * QDP_SOLVE_FULL Newton calls made after this one:
+ *   QDP_ELIM_POINT   one workgroup per point (the matrix in that workgroup's
+ *                    registers, LDS or global memory);
+ *   QDP_ELIM_COLUMNS one single-wavefront workgroup per column of [A | -h],
+ *                    the pivot columns' multipliers passed through device
+ *                    memory, for double and quad double, n <= 128 and
+ *                    points x (n+1) <= 1024 (other calls: one per point);
+ *   QDP_ELIM_AUTO    (default) columns for quad double and for double double
+ *                    past n = 64, where one point's elimination otherwise
+ *                    keeps one compute unit busy longest; one per point
+ *                    elsewhere.
+ * Both give the same pivots and, where the one-per-point kernel is the
+ * register kernel (double double, n <= 64), bit for bit the same results.
+ * QDP_EINVAL for another value. */
+qdp_status qdp_set_elimination(int32_t policy);
 
 /* Kernel timing with HIP events on the call's stream.  After
  * qdp_set_timing(1) (process-wide), every Newton iteration enqueued by

@@ -7,6 +7,9 @@ The Python layer only marshals arguments (``binding``); the compute path is
 """
 
 from .binding import (  # noqa: F401
+    ELIM_AUTO,
+    ELIM_COLUMNS,
+    ELIM_POINT,
     PRED_LEARNED,
     PRED_QUADRATIC,
     PRED_SECANT,
@@ -34,6 +37,7 @@ from .binding import (  # noqa: F401
     newton_step_dev,
     newton_step_noalloc_dev,
     info_from_bytes,
+    set_elimination,
     track_path,
     track_paths,
     version,

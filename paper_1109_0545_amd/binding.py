@@ -151,6 +151,7 @@ SIGNATURES = {
                                    _P]),
     "qdp_arith_batch": (ct.c_int, [ct.c_int32, ct.c_int, ct.c_int64, _P, _P, _P, _P, _P]),
     "qdp_set_timing": (ct.c_int, [ct.c_int32]),
+    "qdp_set_elimination": (ct.c_int, [ct.c_int32]),
     "qdp_homotopy_last_timing": (ct.c_int, [_P, ct.c_int, _D, _D, ct.POINTER(ct.c_int32), _P]),
     "qdp_policy_create": (ct.c_int, [ct.c_int32, _P, _P, _P, _P, ct.POINTER(_P)]),
     "qdp_policy_destroy": (None, [_P]),
@@ -556,6 +557,15 @@ def arith_batch(op: str, prec: int, a, b=None, c=None, stream=None):
     out = torch.empty((count, prec), dtype=a.dtype, device=a.device) if op == "pivot" else torch.empty_like(a)
     _check(lib().qdp_arith_batch(ARITH_OPS[op], prec, count, pa, pb, pc, out.data_ptr(), _stream(stream)))
     return out
+
+
+ELIM_AUTO, ELIM_POINT, ELIM_COLUMNS = 0, 1, 2
+
+
+def set_elimination(policy: int) -> None:
+    """qdp_set_elimination: ELIM_AUTO, ELIM_POINT (one workgroup per point) or
+    ELIM_COLUMNS (one workgroup per column), process-wide."""
+    _check(lib().qdp_set_elimination(int(policy)))
 
 
 def set_timing(on: bool) -> None:

@@ -19,7 +19,9 @@
 
 namespace qdp {
 hipError_t launch_ge_scaled(int L, int n, int B, double *ab, double *scale, double *x, double *dz, NewtonState *st,
-                            hipStream_t s);
+                            double *mc_ws, hipStream_t s);
+void set_ge_policy(int p);
+bool ge_mc_possible(int L, int n, int B);
 hipError_t launch_arith(int op, int L, int64_t count, const double *a, const double *b, const double *c,
                         double *out, hipStream_t s);
 hipError_t launch_init_state(NewtonState *st, int B, double eps, int max_it, const int *mask, hipStream_t s);
@@ -103,6 +105,8 @@ struct Workspace {
   double *y = nullptr;      // [n] values (eval entry points)
   double *jac = nullptr;    // [n][n] Jacobian (eval entry points)
   double *lu = nullptr;     // [bcap] mixed precision: FP64 factors
+  double *mc = nullptr;     // [mc_cap] column-parallel elimination workspaces
+  int mc_cap = 0;
   NewtonState *st = nullptr;  // [bcap]
   double *aux = nullptr;       // [4] predictor distance, blend-label sums
   float *pfeat = nullptr;      // [16] controller features, then [8] network outputs
@@ -127,10 +131,11 @@ static void free_batch(Workspace &w) {
   hipFree(w.part);
   hipFree(w.suppv);
   hipFree(w.lu);
+  hipFree(w.mc);
   hipFree(w.st);
-  w.ab = w.scale = w.part = w.suppv = w.lu = nullptr;
+  w.ab = w.scale = w.part = w.suppv = w.lu = w.mc = nullptr;
   w.st = nullptr;
-  w.bcap = 0;
+  w.bcap = w.mc_cap = 0;
 }
 
 // Workspace of (h, L) able to hold B points; growing it waits for the device
@@ -166,6 +171,14 @@ static qdp_status ensure_ws(qdp_homotopy *h, int L, int B, Workspace **out) {
     if (h->f->supp > 0) HIPCHK(hipMalloc(&w.suppv, Bs * qdp::eval_supp_doubles(L, n, h->f->supp) * sizeof(double)));
     if (mixed_supported(L, n) && qdp::mixed_ws_doubles(n) > 0)
       HIPCHK(hipMalloc(&w.lu, Bs * qdp::mixed_ws_doubles(n) * sizeof(double)));
+    if (qdp::ge_mc_possible(L, n, 1)) {
+      int cap = B;
+      while (cap > 1 && !qdp::ge_mc_possible(L, n, cap)) --cap;
+      const size_t bytes = (size_t)cap * qdp::ge_mc_doubles(L, n) * sizeof(double);
+      HIPCHK(hipMalloc(&w.mc, bytes));
+      HIPCHK(hipMemset(w.mc, 0, bytes));
+      w.mc_cap = cap;
+    }
     w.bcap = B;
   }
   *out = &w;
@@ -440,7 +453,8 @@ static qdp_status enqueue_newton(qdp_homotopy *h, Workspace *w, int L, double t,
     if (mode == QDP_SOLVE_MIXED_IR)
       HIPCHK(qdp::launch_mixed_solve(L, n, B, w->ab, w->scale, x_dev, w->st, w->lu, mixed_refinements(L), st));
     else
-      HIPCHK(qdp::launch_ge_scaled(L, n, B, w->ab, w->scale, x_dev, nullptr, w->st, st));
+      HIPCHK(qdp::launch_ge_scaled(L, n, B, w->ab, w->scale, x_dev, nullptr, w->st, B <= w->mc_cap ? w->mc : nullptr,
+                                   st));
     if (timing) HIPCHK(hipEventRecord(w->ev[3 * it + 2], st));
   }
   return QDP_OK;
@@ -529,7 +543,7 @@ __global__ void k_info_from_state(const NewtonState *s, qdp_newton_info *info) {
 
 // doubles of scratch one point of (h, L, mode) takes, each part rounded up to 32 doubles
 static size_t scratch_need(const qdp_homotopy *h, int L, int mode, size_t *ab, size_t *scale, size_t *part,
-                           size_t *suppv, size_t *lu, size_t *st) {
+                           size_t *suppv, size_t *lu, size_t *mc, size_t *st) {
   const int n = h->f->n;
   auto up = [](size_t d) { return (d + 31) & ~(size_t)31; };
   *ab = up((size_t)n * (n + 1) * 2 * L);
@@ -537,8 +551,9 @@ static size_t scratch_need(const qdp_homotopy *h, int L, int mode, size_t *ab, s
   *part = up(qdp::eval_part_doubles(L, n, 1));
   *suppv = h->f->supp > 0 ? up(qdp::eval_supp_doubles(L, n, h->f->supp)) : 0;
   *lu = mode == QDP_SOLVE_MIXED_IR ? up(qdp::mixed_ws_doubles(n)) : 0;
+  *mc = mode == QDP_SOLVE_FULL && qdp::ge_mc_possible(L, n, 1) ? up(qdp::ge_mc_doubles(L, n)) : 0;
   *st = up((sizeof(NewtonState) + sizeof(double) - 1) / sizeof(double));
-  return *ab + *scale + *part + *suppv + *lu + *st;
+  return *ab + *scale + *part + *suppv + *lu + *mc + *st;
 }
 
 extern "C" qdp_status qdp_newton_step_noalloc_dev(const qdp_homotopy *hc, double t, double *x, qdp_prec prec,
@@ -547,8 +562,8 @@ extern "C" qdp_status qdp_newton_step_noalloc_dev(const qdp_homotopy *hc, double
   qdp_status s = newton_checks(hc, t, x, (int)prec, mode, eps, max_it);
   if (s != QDP_OK) return s;
   const int L = (int)prec;
-  size_t nab, nsc, npt, nsv, nlu, nst;
-  const size_t need = scratch_need(hc, L, mode, &nab, &nsc, &npt, &nsv, &nlu, &nst);
+  size_t nab, nsc, npt, nsv, nlu, nmc, nst;
+  const size_t need = scratch_need(hc, L, mode, &nab, &nsc, &npt, &nsv, &nlu, &nmc, &nst);
   if (need > kScratchDoubles)
     return fail(QDP_EINVAL, "this system needs " + std::to_string(need * sizeof(double)) +
                                 " bytes of Newton workspace; the no-allocation entry point has " +
@@ -563,7 +578,9 @@ extern "C" qdp_status qdp_newton_step_noalloc_dev(const qdp_homotopy *hc, double
   w.part = npt > 0 ? w.scale + nsc : nullptr;
   w.suppv = nsv > 0 ? w.scale + nsc + npt : nullptr;
   w.lu = nlu > 0 ? w.scale + nsc + npt + nsv : nullptr;
-  w.st = reinterpret_cast<NewtonState *>(w.scale + nsc + npt + nsv + nlu);
+  w.mc = nmc > 0 ? w.scale + nsc + npt + nsv + nlu : nullptr;
+  w.mc_cap = nmc > 0 ? 1 : 0;
+  w.st = reinterpret_cast<NewtonState *>(w.scale + nsc + npt + nsv + nlu + nmc);
   auto *h = const_cast<qdp_homotopy *>(hc);
   hipStream_t st = (hipStream_t)stream;
   if ((s = enqueue_newton(h, &w, L, t, x, 1, mode, eps, max_it, st, nullptr, nullptr, false)) != QDP_OK) return s;
@@ -650,6 +667,12 @@ extern "C" qdp_status qdp_newton_step(const qdp_homotopy *hc, double t, double *
   HIPCHK(hipMemcpyAsync(&ns, w->st, sizeof(ns), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (info) info_from_state(ns, info);
+  return QDP_OK;
+}
+
+extern "C" qdp_status qdp_set_elimination(int32_t policy) {
+  if (policy < QDP_ELIM_AUTO || policy > QDP_ELIM_COLUMNS) return fail(QDP_EINVAL, "policy must be 0, 1 or 2");
+  qdp::set_ge_policy(policy);
   return QDP_OK;
 }
 

@@ -53,6 +53,32 @@ struct EvalSplit {
 };
 constexpr int kMaxEvalParts = 8;
 
+// Column-parallel elimination (one workgroup per column of each point): ws
+// holds B per-point workspaces of ge_mc_doubles(L, n), epoch tags this
+// launch's flags.  ws == nullptr: one workgroup per point.
+struct GeMc {
+  double *ws;
+  unsigned epoch;
+};
+
+// Per-point workspace of the column-parallel elimination, in doubles
+// (RMAX = 64 rows per lane slot, 128 past n = 64):
+//   mult [n][2L][RMAX]  multipliers of each column
+//   tri  [2L][TT]       scaled U packed by columns (column c: pivot-order
+//                       rows 0..c-1 at c(c-1)/2), TT = n(n-1)/2 + 1
+//   invp [2L][RMAX]     pivot inverses by column
+//   pmag [RMAX]         |Re|+|Im| of each pivot's leading limb
+//   ctl  [RMAX]         int2: pivot row, zero-pivot flag
+//   pub  [RMAX]         u64 flag: column published
+//   fin  [RMAX]         u64 flag: column's triangle stored (or failed)
+__host__ __device__ inline int mc_rows(int n) { return n <= 64 ? 64 : 128; }
+__host__ __device__ inline size_t mc_tri_doubles(int n) { return (size_t)n * (n - 1) / 2 + 1; }
+__host__ __device__ inline size_t ge_mc_doubles(int L, int n) {
+  const size_t R = (size_t)mc_rows(n), E2 = 2 * (size_t)L;
+  const size_t d = (size_t)n * E2 * R + E2 * mc_tri_doubles(n) + E2 * R + 4 * R;
+  return (d + 31) & ~(size_t)31;
+}
+
 // Homotopy h = t f + (1-t) gamma (x^d - 1); homotopy = 0 evaluates f alone.
 struct HomArgs {
   int homotopy;

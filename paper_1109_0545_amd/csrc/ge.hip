@@ -1,11 +1,38 @@
-// Elimination dispatch by precision.
+// Elimination dispatch by precision, and the choice between one workgroup
+// per point and one workgroup per column.
+#include <atomic>
+
 #include "common.hpp"
 
 namespace qdp {
 
-hipError_t launch_ge_f64(int, int, double *, double *, double *, double *, NewtonState *, hipStream_t);
-hipError_t launch_ge_dd(int, int, double *, double *, double *, double *, NewtonState *, hipStream_t);
-hipError_t launch_ge_qd(int, int, double *, double *, double *, double *, NewtonState *, hipStream_t);
+hipError_t launch_ge_f64(int, int, double *, double *, double *, double *, NewtonState *, const GeMc &, hipStream_t);
+hipError_t launch_ge_dd(int, int, double *, double *, double *, double *, NewtonState *, const GeMc &, hipStream_t);
+hipError_t launch_ge_qd(int, int, double *, double *, double *, double *, NewtonState *, const GeMc &, hipStream_t);
+
+// All (n+1) x B workgroups of a column-parallel elimination wait on one
+// another, so they must all be resident at once: one wavefront each, at most
+// this many per launch (four per compute unit).
+constexpr long kMcMaxGroups = 1024;
+static std::atomic<int> g_ge_policy{0};
+static std::atomic<unsigned> g_mc_epoch{0};
+
+void set_ge_policy(int p) { g_ge_policy.store(p); }
+int ge_policy() { return g_ge_policy.load(); }
+
+// whether a column-parallel workspace can serve (L, n, B) at all
+bool ge_mc_possible(int L, int n, int B) {
+  return (L == 2 || L == 4) && n >= 1 && n <= 128 && B >= 1 && (long)B * (n + 1) <= kMcMaxGroups;
+}
+// policy 0 (default): column-parallel where one point's elimination keeps one
+// compute unit busy longest (quad double; double double past 64 rows, whose
+// matrix does not fit in one compute unit's registers); 1: never; 2: wherever
+// possible
+static bool ge_mc_chosen(int L, int n, int B) {
+  const int p = g_ge_policy.load();
+  if (p == 1 || !ge_mc_possible(L, n, B)) return false;
+  return p == 2 || L == 4 || n > 64;
+}
 
 size_t ge_lds_bytes(int L, int n, bool in_lds) {
   size_t d = (size_t)2 * n * 2 * L + 16;  // inverses + rhs + reduction
@@ -14,13 +41,16 @@ size_t ge_lds_bytes(int L, int n, bool in_lds) {
 }
 
 // B points, one workgroup each (see GeArgs for the batch layout)
+// (mc_ws: B column-parallel workspaces, or nullptr)
 hipError_t launch_ge_scaled(int L, int n, int B, double *ab, double *scale, double *x, double *dz, NewtonState *st,
-                            hipStream_t s) {
+                            double *mc_ws, hipStream_t s) {
   if (B < 1) return hipErrorInvalidValue;
+  GeMc mc{nullptr, 0u};
+  if (mc_ws && ge_mc_chosen(L, n, B)) mc = GeMc{mc_ws, g_mc_epoch.fetch_add(1u) + 1u};
   switch (L) {
-    case 1: return launch_ge_f64(n, B, ab, scale, x, dz, st, s);
-    case 2: return launch_ge_dd(n, B, ab, scale, x, dz, st, s);
-    case 4: return launch_ge_qd(n, B, ab, scale, x, dz, st, s);
+    case 1: return launch_ge_f64(n, B, ab, scale, x, dz, st, mc, s);
+    case 2: return launch_ge_dd(n, B, ab, scale, x, dz, st, mc, s);
+    case 4: return launch_ge_qd(n, B, ab, scale, x, dz, st, mc, s);
   }
   return hipErrorInvalidValue;
 }

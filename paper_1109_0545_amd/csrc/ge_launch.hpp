@@ -1,8 +1,10 @@
 // Elimination launcher shared by the per-precision translation units: the
-// register-resident kernel (ge_reg.hpp) when the augmented matrix fits in one
-// workgroup's registers, else the LDS / global-memory kernel (ge_kernel.hpp).
+// column-parallel kernel (ge_mc.hpp) when the caller chose it (GeMc), else
+// the register-resident kernel (ge_reg.hpp) when the augmented matrix fits in
+// one workgroup's registers, else the LDS / global-memory kernel
+// (ge_kernel.hpp).
 #pragma once
-#include "ge_reg.hpp"
+#include "ge_mc.hpp"
 
 namespace qdp {
 
@@ -20,8 +22,18 @@ static hipError_t launch_ge_reg(int n, int B, const GeArgs<L> &a, hipStream_t s)
 
 template <int L>
 static hipError_t launch_ge_L(int n, int B, double *ab, double *scale, double *x, double *dz, NewtonState *st,
-                              hipStream_t s) {
+                              const GeMc &mc, hipStream_t s) {
   GeArgs<L> a{n, ab, scale, x, dz, st};
+  if constexpr (L == 2 || L == 4) {
+    if (mc.ws) {
+      if (n < 1 || n > 128) return hipErrorInvalidValue;
+      if (n <= 64)
+        hipLaunchKernelGGL((k_ge_mc<L, 1>), dim3(n + 1, B), dim3(64), 0, s, a, mc.ws, mc.epoch);
+      else
+        hipLaunchKernelGGL((k_ge_mc<L, 2>), dim3(n + 1, B), dim3(64), 0, s, a, mc.ws, mc.epoch);
+      return hipGetLastError();
+    }
+  }
   // quad double keeps the LDS kernel: its pivot step (inverse and products in
   // four limbs) is long enough that the register kernel measured slower
   if constexpr (L == 1) {
