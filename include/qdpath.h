@@ -53,7 +53,7 @@ typedef enum {
 
 typedef enum { QDP_SOLVE_FULL = 0, QDP_SOLVE_MIXED_IR = 1 } qdp_solve;
 typedef enum { QDP_PRED_SECANT = 0, QDP_PRED_LEARNED = 1, QDP_PRED_QUADRATIC = 2 } qdp_pred;
-typedef enum { QDP_ELIM_AUTO = 0, QDP_ELIM_POINT = 1, QDP_ELIM_COLUMNS = 2 } qdp_elim;
+typedef enum { QDP_ELIM_AUTO = 0, QDP_ELIM_POINT = 1, QDP_ELIM_COLUMNS = 2, QDP_ELIM_BLOCKS = 3 } qdp_elim;
 
 typedef struct qdp_system qdp_system;
 typedef struct qdp_homotopy qdp_homotopy;
@@ -349,6 +349,10 @@ qdp_status qdp_arith_batch(int32_t op, qdp_prec prec, int64_t count, const doubl
  *                    the pivot columns' multipliers passed through device
  *                    memory, for double and quad double, n <= 128 and
  *                    points x (n+1) <= 1024 (other calls: one per point);
+ *   QDP_ELIM_BLOCKS  double double, n <= 64: blocks of 16 columns per
+ *                    workgroup (the register elimination inside a block,
+ *                    device memory between blocks), points x blocks <= 128;
+ *                    other calls as QDP_ELIM_COLUMNS;
  *   QDP_ELIM_AUTO    (default) columns for quad double and for double double
  *                    past n = 64, where one point's elimination otherwise
  *                    keeps one compute unit busy longest; one per point

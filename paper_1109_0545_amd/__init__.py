@@ -8,6 +8,7 @@ The Python layer only marshals arguments (``binding``); the compute path is
 
 from .binding import (  # noqa: F401
     ELIM_AUTO,
+    ELIM_BLOCKS,
     ELIM_COLUMNS,
     ELIM_POINT,
     PRED_LEARNED,

@@ -559,12 +559,13 @@ def arith_batch(op: str, prec: int, a, b=None, c=None, stream=None):
     return out
 
 
-ELIM_AUTO, ELIM_POINT, ELIM_COLUMNS = 0, 1, 2
+ELIM_AUTO, ELIM_POINT, ELIM_COLUMNS, ELIM_BLOCKS = 0, 1, 2, 3
 
 
 def set_elimination(policy: int) -> None:
-    """qdp_set_elimination: ELIM_AUTO, ELIM_POINT (one workgroup per point) or
-    ELIM_COLUMNS (one workgroup per column), process-wide."""
+    """qdp_set_elimination: ELIM_AUTO, ELIM_POINT (one workgroup per point),
+    ELIM_COLUMNS (one workgroup per column) or ELIM_BLOCKS (blocks of columns
+    per workgroup), process-wide."""
     _check(lib().qdp_set_elimination(int(policy)))
 
 

@@ -671,7 +671,7 @@ extern "C" qdp_status qdp_newton_step(const qdp_homotopy *hc, double t, double *
 }
 
 extern "C" qdp_status qdp_set_elimination(int32_t policy) {
-  if (policy < QDP_ELIM_AUTO || policy > QDP_ELIM_COLUMNS) return fail(QDP_EINVAL, "policy must be 0, 1 or 2");
+  if (policy < QDP_ELIM_AUTO || policy > QDP_ELIM_BLOCKS) return fail(QDP_EINVAL, "policy must be 0, 1, 2 or 3");
   qdp::set_ge_policy(policy);
   return QDP_OK;
 }

@@ -59,6 +59,7 @@ constexpr int kMaxEvalParts = 8;
 struct GeMc {
   double *ws;
   unsigned epoch;
+  int blocks;  // 1: blocks of columns per workgroup (double double, n <= 64)
 };
 
 // Per-point workspace of the column-parallel elimination, in doubles

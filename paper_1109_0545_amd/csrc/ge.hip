@@ -24,14 +24,22 @@ int ge_policy() { return g_ge_policy.load(); }
 bool ge_mc_possible(int L, int n, int B) {
   return (L == 2 || L == 4) && n >= 1 && n <= 128 && B >= 1 && (long)B * (n + 1) <= kMcMaxGroups;
 }
+// blocks of 16 columns per workgroup (double double, n <= 64): one workgroup
+// per compute unit (its LDS), at most this many per launch
+constexpr long kMcbMaxGroups = 128;
+static bool ge_mcb_possible(int L, int n, int B) {
+  return L == 2 && n >= 1 && n <= 64 && B >= 1 && (long)B * ((n + 16) / 16) <= kMcbMaxGroups;
+}
 // policy 0 (default): column-parallel where one point's elimination keeps one
 // compute unit busy longest (quad double; double double past 64 rows, whose
-// matrix does not fit in one compute unit's registers); 1: never; 2: wherever
-// possible
-static bool ge_mc_chosen(int L, int n, int B) {
+// matrix does not fit in one compute unit's registers); 1: never; 2: columns
+// wherever possible; 3: blocks of columns where possible, else as 2
+static GeMc ge_mc_choice(int L, int n, int B, double *ws) {
   const int p = g_ge_policy.load();
-  if (p == 1 || !ge_mc_possible(L, n, B)) return false;
-  return p == 2 || L == 4 || n > 64;
+  if (!ws || p == 1 || !ge_mc_possible(L, n, B)) return GeMc{nullptr, 0u, 0};
+  if (p == 3 && ge_mcb_possible(L, n, B)) return GeMc{ws, g_mc_epoch.fetch_add(1u) + 1u, 1};
+  if (p == 2 || p == 3 || L == 4 || n > 64) return GeMc{ws, g_mc_epoch.fetch_add(1u) + 1u, 0};
+  return GeMc{nullptr, 0u, 0};
 }
 
 size_t ge_lds_bytes(int L, int n, bool in_lds) {
@@ -45,8 +53,7 @@ size_t ge_lds_bytes(int L, int n, bool in_lds) {
 hipError_t launch_ge_scaled(int L, int n, int B, double *ab, double *scale, double *x, double *dz, NewtonState *st,
                             double *mc_ws, hipStream_t s) {
   if (B < 1) return hipErrorInvalidValue;
-  GeMc mc{nullptr, 0u};
-  if (mc_ws && ge_mc_chosen(L, n, B)) mc = GeMc{mc_ws, g_mc_epoch.fetch_add(1u) + 1u};
+  const GeMc mc = ge_mc_choice(L, n, B, mc_ws);
   switch (L) {
     case 1: return launch_ge_f64(n, B, ab, scale, x, dz, st, mc, s);
     case 2: return launch_ge_dd(n, B, ab, scale, x, dz, st, mc, s);

@@ -1,9 +1,10 @@
-"""The column-parallel elimination (one workgroup per column of [A | -h],
-Section 4's GE and Back_Subs spread over compute units) against the
-one-workgroup-per-point kernels: bit for bit where the latter is the register
-kernel (double double, n <= 64: same pivots, same updates in the same order),
-within the one-step bound elsewhere; batches equal single calls; singular and
-non-finite cases reported as the point kernels report them."""
+"""The column-parallel eliminations (one workgroup per column of [A | -h], or
+blocks of 16 columns per workgroup: Section 4's GE and Back_Subs spread over
+compute units) against the one-workgroup-per-point kernels: bit for bit where
+the latter is the register kernel (double double, n <= 64: same pivots, same
+updates in the same order), within the one-step bound elsewhere; batches equal
+single calls; singular and non-finite cases reported as the point kernels
+report them."""
 
 import mpmath
 import numpy as np
@@ -37,15 +38,18 @@ def _step(q, H, x, L, policy_value, set_policy, max_it, t=0.6):
     return q.newton_step(H, t, x, L, eps=0.0, max_it=max_it)
 
 
-@pytest.mark.parametrize("n", [1, 2, 8, 33, 57, 64])
-def test_columns_equal_register_kernel_bit_for_bit(n, policy):
+@pytest.mark.parametrize("layout", ["columns", "blocks"])
+@pytest.mark.parametrize("n", [1, 2, 8, 15, 16, 17, 33, 48, 57, 64])
+def test_columns_equal_register_kernel_bit_for_bit(n, layout, policy):
+    # blocks of 16 columns: one workgroup (n = 15), the right-hand side alone
+    # in the second (n = 16), ragged last blocks, four blocks and b (n = 64)
     import paper_1109_0545_amd as q
 
     s, H = _system(n, 2, 500 + n)
     x = random_point(n, 2, seed=510 + n, spread=0.05)
-    say("columns vs register kernel, DD n", n)
+    say(layout, "vs register kernel, DD n", n)
     xp, ip = _step(q, H, x, 2, q.ELIM_POINT, policy, 3)
-    xc, ic = _step(q, H, x, 2, q.ELIM_COLUMNS, policy, 3)
+    xc, ic = _step(q, H, x, 2, q.ELIM_COLUMNS if layout == "columns" else q.ELIM_BLOCKS, policy, 3)
     assert ic["iterations"] == 3 and not ic["singular"] and not ic["nonfinite"]
     assert np.array_equal(xp, xc)
     assert ip == ic, (ip, ic)
@@ -79,8 +83,10 @@ def test_columns_agree_with_point_kernel(n, L, policy):
     assert d <= bound, (d, bound)
 
 
-@pytest.mark.parametrize("n,L,B,m", [(57, 2, 3, 6), (64, 4, 4, 2), (128, 2, 2, 6)])
-def test_columns_batch_equals_single_calls(n, L, B, m, policy):
+@pytest.mark.parametrize("n,L,B,m,layout", [(57, 2, 3, 6, "columns"), (64, 4, 4, 2, "columns"),
+                                            (128, 2, 2, 6, "columns"), (57, 2, 3, 6, "blocks"),
+                                            (64, 2, 5, 6, "blocks")])
+def test_columns_batch_equals_single_calls(n, L, B, m, layout, policy):
     # m monomials per polynomial, fewer than a workgroup part's minimum of two
     # wavefronts' worth (lanes per monomial: 16 here in double double, 32 in
     # quad double), so the evaluation is never split over workgroups (its
@@ -93,8 +99,8 @@ def test_columns_batch_equals_single_calls(n, L, B, m, policy):
     s = make_system(n, m, 2, L, 540 + n)
     H = q.Homotopy(q.System.from_synth(s), s.gamma)
     xs = np.stack([random_point(n, L, seed=550 + b, spread=0.05) for b in range(B)])
-    policy(q.ELIM_COLUMNS)
-    say("columns batch n", n, "L", L, "B", B)
+    policy(q.ELIM_COLUMNS if layout == "columns" else q.ELIM_BLOCKS)
+    say(layout, "batch n", n, "L", L, "B", B)
     stream = torch.cuda.current_stream()
     xd = torch.from_numpy(xs).cuda()
     q.newton_batch_dev(H, 0.4, xd, B, L, eps=0.0, max_it=2, stream=stream)
@@ -106,21 +112,23 @@ def test_columns_batch_equals_single_calls(n, L, B, m, policy):
         assert infos[b] == i1, (b, infos[b], i1)
 
 
+@pytest.mark.parametrize("layout", ["columns", "blocks"])
 @pytest.mark.parametrize("name,prec", [("n8_dd", 2), ("n64_dd", 2)])
-def test_columns_report_singular_columns(name, prec, policy):
+def test_columns_report_singular_columns(name, prec, layout, policy):
     # t = 0, x_k = 0 (d_k >= 2), the other coordinates on the unit circle:
-    # column k is the first without a nonzero pivot
+    # column k is the first without a nonzero pivot (in the first, a middle
+    # and the last block)
     import paper_1109_0545_amd as q
 
     s = config_system(CONFIGS[name])
     H = q.Homotopy(q.System.from_synth(s), s.gamma)
     cand = [k for k in range(s.n) if s.degrees[k] >= 2]
-    policy(q.ELIM_COLUMNS)
+    policy(q.ELIM_COLUMNS if layout == "columns" else q.ELIM_BLOCKS)
     for k in sorted({cand[0], cand[len(cand) // 2], cand[-1]}):
         x = np.zeros((s.n, 2, prec))
         x[:, 0, 0] = 1.0
         x[k, 0, 0] = 0.0
-        say(f"columns singular column {k} {name}")
+        say(f"{layout} singular column {k} {name}")
         xg, info = q.newton_step(H, 0.0, x, prec, eps=1e-10, max_it=4)
         assert info["singular"] == 1 and not info["success"] and info["iterations"] == 1, (k, info)
         assert np.isinf(info["cond_est"])
@@ -137,7 +145,7 @@ def test_columns_report_nonfinite_residual(L, policy):
     x = np.zeros((16, 2, L))
     x[:, 0, 0] = 1e100
     out = {}
-    for pol in (q.ELIM_POINT, q.ELIM_COLUMNS):
+    for pol in (q.ELIM_POINT, q.ELIM_COLUMNS) + ((q.ELIM_BLOCKS,) if L == 2 else ()):
         policy(pol)
         say("columns non-finite h, policy", pol, "L", L)
         xg, info = q.newton_step(H, 0.5, x, L, eps=1e-10, max_it=3)
@@ -152,4 +160,4 @@ def test_set_elimination_rejects_unknown_policy():
     import paper_1109_0545_amd as q
 
     with pytest.raises(q.QdpError):
-        q.set_elimination(3)
+        q.set_elimination(4)
