@@ -353,10 +353,11 @@ qdp_status qdp_arith_batch(int32_t op, qdp_prec prec, int64_t count, const doubl
  *                    workgroup (the register elimination inside a block,
  *                    device memory between blocks), points x blocks <= 128;
  *                    other calls as QDP_ELIM_COLUMNS;
- *   QDP_ELIM_AUTO    (default) columns for quad double and for double double
- *                    past n = 64, where one point's elimination otherwise
- *                    keeps one compute unit busy longest; one per point
- *                    elsewhere.
+ *   QDP_ELIM_AUTO    (default) blocks for double double at 48 < n <= 64;
+ *                    columns for quad double and for double double past
+ *                    n = 64, where one point's elimination otherwise keeps
+ *                    one compute unit busy longest; one per point elsewhere
+ *                    (and wherever the chosen layout's limits are exceeded).
  * Both give the same pivots and, where the one-per-point kernel is the
  * register kernel (double double, n <= 64), bit for bit the same results.
  * QDP_EINVAL for another value. */

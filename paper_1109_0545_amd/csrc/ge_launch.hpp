@@ -27,7 +27,7 @@ static hipError_t launch_ge_L(int n, int B, double *ab, double *scale, double *x
   if constexpr (L == 2) {
     if (mc.ws && mc.blocks) {
       if (n < 1 || n > 64) return hipErrorInvalidValue;
-      constexpr int NW = 4, CPW = 4;
+      constexpr int NW = 8, CPW = 2;
       const size_t lds = ge_mcb_lds_bytes(L, n, NW);
       hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ge_mcb<L, NW, CPW>),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
