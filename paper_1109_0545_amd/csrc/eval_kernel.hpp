@@ -115,9 +115,21 @@ __device__ void eval_finish(const EvalArgs<L> &a, int b, int i, int col, C<L> s,
 // Second stage of a split evaluation: row i of point b is the sum of its P
 // partial rows in part order, then blended (with the start-system powers the
 // first stage's extra workgroup formed) and stored.
+// Row of workgroup slot s < n.  Workgroups go to the eight XCDs in turn (slot
+// s to XCD s mod 8), and each XCD has its own L2; with n a multiple of 8 the
+// rows are dealt so that the XCD of slot s holds the n/8 consecutive rows
+// (s mod 8) n/8 ..: the rows that share a cache line of a column of [A | -h]
+// are then written through one L2, which merges them into whole lines, and
+// the parts of a split row (slot part n + s) share the XCD of its sum.
+__device__ inline int eval_row_of_slot(int s, int n) {
+  if (n & 7) return s;
+  const int R = n >> 3;
+  return (s & 7) * R + (s >> 3);
+}
+
 template <int L>
 __global__ __launch_bounds__(256) void k_eval_sum(EvalArgs<L> a) {
-  const int b = blockIdx.y, i = blockIdx.x;
+  const int b = blockIdx.y, i = eval_row_of_slot(blockIdx.x, a.s.n);
   if (a.gate && !a.gate[b].active) return;
   const int n = a.s.n;
   const size_t rec = part_record(n, L);
@@ -277,7 +289,8 @@ __global__ __launch_bounds__(NT + 64) void k_eval(EvalArgs<L> a) {
   }
   __syncthreads();
 
-  const int i = blockIdx.x / a.P, part = blockIdx.x - i * a.P;
+  // part-major slots: part p of row i in slot p n + s(i), on the XCD of row i's sum
+  const int part = blockIdx.x / n, i = eval_row_of_slot(blockIdx.x - part * n, n);
   const int m0 = a.s.offsets[i], m1 = a.s.offsets[i + 1];
   const int chunk = (m1 - m0 + a.P - 1) / a.P;
   const int t0 = min(m1, m0 + part * chunk), t1 = min(m1, t0 + chunk);
