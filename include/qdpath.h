@@ -349,17 +349,18 @@ qdp_status qdp_arith_batch(int32_t op, qdp_prec prec, int64_t count, const doubl
  *                    the pivot columns' multipliers passed through device
  *                    memory, for double and quad double, n <= 128 and
  *                    points x (n+1) <= 1024 (other calls: one per point);
- *   QDP_ELIM_BLOCKS  double double, n <= 64: blocks of 16 columns per
- *                    workgroup (the register elimination inside a block,
+ *   QDP_ELIM_BLOCKS  double and quad double, n <= 64: blocks of 16 columns
+ *                    per workgroup (the register elimination inside a block,
  *                    device memory between blocks), points x blocks <= 128;
  *                    other calls as QDP_ELIM_COLUMNS;
- *   QDP_ELIM_AUTO    (default) blocks for double double at 48 < n <= 64;
- *                    columns for quad double and for double double past
- *                    n = 64, where one point's elimination otherwise keeps
- *                    one compute unit busy longest; one per point elsewhere
- *                    (and wherever the chosen layout's limits are exceeded).
- * Both give the same pivots and, where the one-per-point kernel is the
- * register kernel (double double, n <= 64), bit for bit the same results.
+ *   QDP_ELIM_AUTO    (default) blocks for double double at 48 < n <= 64 and
+ *                    for quad double up to n = 64; columns past n = 64 (quad
+ *                    double, and double double); one per point elsewhere (and
+ *                    wherever the chosen layout's limits are exceeded).
+ * Blocks and columns give bit for bit the same results, and so does one per
+ * point where it is the register kernel (double double, n <= 64); elsewhere
+ * one per point compares pivot magnitudes in full and may order near ties
+ * differently.
  * QDP_EINVAL for another value. */
 qdp_status qdp_set_elimination(int32_t policy);
 

@@ -2,9 +2,9 @@
 // substitution and the update z := z + dz of one Newton iteration
 // (Algorithm 4.1 and the description of GE / Back_Subs in Section 4).
 //
-// Section 4 lets one thread pick the pivot (the largest number in the
-// current column) while the others wait, then every thread updates its own
-// rows, with a barrier per column.  On one CDNA4 workgroup the pivot search
+// In Section 4 a single thread chooses the pivot row by magnitude within the
+// column while the other threads wait; then all threads update their rows,
+// and the threads synchronise once per column.  On one CDNA4 workgroup the pivot search
 // and the pivot's inverse would then sit on the critical path of every
 // column, so this kernel looks one column ahead:
 //   * during step j, wavefront 0 updates column j+1 of every remaining row

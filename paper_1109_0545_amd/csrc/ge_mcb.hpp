@@ -13,7 +13,7 @@
 //   * Steps of earlier blocks: the forwarding wavefront waits for their
 //     device flags (several steps per poll when they are already raised),
 //     reads pivot rows and multipliers from device memory and places them in
-//     the workgroup's LDS ring of KRING multiplier vectors, raising the LDS
+//     the workgroup's LDS ring of multiplier vectors, raising the LDS
 //     step counter; the column wavefronts cannot tell these steps from their
 //     own.
 //   * Steps of the block's own columns: as in the register kernel (the owner
@@ -37,20 +37,22 @@
 namespace qdp {
 
 // LDS of one block workgroup, in doubles (then ints):
-//   ring [KRING][2L][64]  multipliers of the last KRING steps
+//   ring [KR][2L][64]     multipliers of the last KR steps (KR = 8, 4 in quad
+//                         double, whose gathered triangle takes 129 KB at n = 64)
 //   tri  [2L][TT]         (last block) scaled U, packed by columns
 //   rhs  [2L][64]         (last block) scaled right-hand side, pivot order
 //   ctl  [64] int2        pivot row and flag of every step (flag 2: a device
 //                         wait ran out of time)
 //   pub, rd[NW]           steps in the ring; steps read by each column wavefront
+__host__ __device__ inline constexpr int mcb_ring(int L) { return L == 4 ? 4 : KRING; }
 __host__ __device__ inline size_t ge_mcb_lds_bytes(int L, int n, int NW) {
-  const size_t d = (size_t)(KRING * 2 * L + 2 * L) * 64 + 2 * (size_t)L * mc_tri_doubles(n);
+  const size_t d = (size_t)(mcb_ring(L) * 2 * L + 2 * L) * 64 + 2 * (size_t)L * mc_tri_doubles(n);
   return d * sizeof(double) + 64 * sizeof(int2) + (size_t)(2 + NW) * sizeof(int);
 }
 
 template <int L, int NW, int CPW, int K = 4>
 __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *ws, unsigned epoch) {
-  constexpr int RPL = 1, RMAX = 64, E2 = 2 * L, WB = NW * CPW;
+  constexpr int RPL = 1, RMAX = 64, E2 = 2 * L, WB = NW * CPW, KR = mcb_ring(L);
   const int n = a.n, g = blockIdx.x;
   const size_t b = blockIdx.y;
   NewtonState *const nst = a.st ? a.st + b : nullptr;
@@ -75,7 +77,7 @@ __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *w
 
   extern __shared__ double smem[];
   double *const ring = smem;
-  double *const ltri = ring + KRING * E2 * RMAX;
+  double *const ltri = ring + KR * E2 * RMAX;
   double *const rhs = ltri + E2 * TT;
   int2 *const ctl = reinterpret_cast<int2 *>(rhs + E2 * RMAX);
   int *const pub = reinterpret_cast<int *>(ctl + RMAX);
@@ -156,7 +158,7 @@ __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *w
     while (j < c0) {
       if (!mc_wait(gpub + j, tag, true)) {
         // out of time: a failure entry stops the column wavefronts
-        const int need = j - KRING + 1;
+        const int need = j - KR + 1;
         int rdl = lane < NW ? __hip_atomic_load(rd + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : need;
         while (__ballot(rdl < need) != 0ull)
           rdl = lane < NW ? __hip_atomic_load(rd + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : need;
@@ -185,11 +187,11 @@ __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *w
         if (k >= r || sing) break;
         const int jj = j + k;
         const int px = __builtin_amdgcn_readlane(ck.x, k), py = __builtin_amdgcn_readlane(ck.y, k);
-        const int need = jj - KRING + 1;
+        const int need = jj - KR + 1;
         int rdl = lane < NW ? __hip_atomic_load(rd + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : need;
         while (__ballot(rdl < need) != 0ull)
           rdl = lane < NW ? __hip_atomic_load(rd + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : need;
-        pstore<L>(ring + (jj % KRING) * E2 * RMAX + lane, RMAX, lk[k]);
+        pstore<L>(ring + (jj % KR) * E2 * RMAX + lane, RMAX, lk[k]);
         if (lane == 0) ctl[jj] = make_int2(px, py);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         if (lane == 0) __hip_atomic_store(pub, jj + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -232,7 +234,7 @@ __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *w
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
       const int2 cj = ctl[j];
       C<L> l[RPL];
-      l[0] = pload<L>(ring + (j % KRING) * E2 * RMAX + lane, RMAX);
+      l[0] = pload<L>(ring + (j % KR) * E2 * RMAX + lane, RMAX);
       const int sgj = __builtin_amdgcn_readfirstlane(cj.y);
       const int p = __builtin_amdgcn_readfirstlane(cj.x);
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -246,7 +248,7 @@ __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *w
       l[0] = cselect<L>(upd, l[0], czero<L>());
       if (owner) {
         __builtin_amdgcn_s_setprio(2);
-        const int need = j1 - KRING + 1;
+        const int need = j1 - KR + 1;
         int rdl = lane < NW ? __hip_atomic_load(rd + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : need;
         const C<L> uv = reg_row<L, RPL>(A[0], p);
         A[0][0] = cfms<L>(A[0][0], l[0], uv);
@@ -256,7 +258,7 @@ __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *w
         double pk;
         int pn;
         bool cand[1] = {upd};
-        reg_pivot<L, RPL>(A[0], cand, j1, ring + (j1 % KRING) * E2 * RMAX, ctl, inv, pk, pn);
+        reg_pivot<L, RPL>(A[0], cand, j1, ring + (j1 % KR) * E2 * RMAX, ctl, inv, pk, pn);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         if (lane == 0) __hip_atomic_store(pub, j1 + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         __builtin_amdgcn_s_setprio(0);

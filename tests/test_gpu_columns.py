@@ -55,6 +55,23 @@ def test_columns_equal_register_kernel_bit_for_bit(n, layout, policy):
     assert ip == ic, (ip, ic)
 
 
+@pytest.mark.parametrize("n", [1, 12, 17, 40, 64])
+def test_quad_double_blocks_equal_columns_bit_for_bit(n, policy):
+    # the block and column layouts in quad double: same pivots, same updates,
+    # same substitution; the default takes blocks
+    import paper_1109_0545_amd as q
+
+    s, H = _system(n, 4, 570 + n)
+    x = random_point(n, 4, seed=580 + n, spread=0.05)
+    say("QD blocks vs columns n", n)
+    xc, ic = _step(q, H, x, 4, q.ELIM_COLUMNS, policy, 2)
+    xb, ib = _step(q, H, x, 4, q.ELIM_BLOCKS, policy, 2)
+    xa, ia = _step(q, H, x, 4, q.ELIM_AUTO, policy, 2)
+    assert ib["iterations"] == 2 and not ib["singular"] and not ib["nonfinite"]
+    assert np.array_equal(xb, xc) and ib == ic, (ib, ic)
+    assert np.array_equal(xa, xb) and ia == ib
+
+
 @pytest.mark.parametrize("n,L", [(12, 4), (64, 4), (65, 2), (100, 2), (128, 2), (128, 4)])
 def test_columns_agree_with_point_kernel(n, L, policy):
     # different pivot keys (the point kernel compares full FP64 magnitudes,
@@ -69,7 +86,7 @@ def test_columns_agree_with_point_kernel(n, L, policy):
     xp, ip = _step(q, H, x, L, q.ELIM_POINT, policy, 1)
     xc, ic = _step(q, H, x, L, q.ELIM_COLUMNS, policy, 1)
     xa, ia = _step(q, H, x, L, q.ELIM_AUTO, policy, 1)
-    assert np.array_equal(xa, xc) and ia == ic  # the default takes columns here
+    assert np.array_equal(xa, xc) and ia == ic  # the default takes columns or blocks here
     assert not ic["singular"] and not ic["nonfinite"] and ic["iterations"] == 1
     assert ic["residual_first"] == ip["residual_first"]
     u = 2.0 ** (-53 * L)
@@ -85,7 +102,7 @@ def test_columns_agree_with_point_kernel(n, L, policy):
 
 @pytest.mark.parametrize("n,L,B,m,layout", [(57, 2, 3, 6, "columns"), (64, 4, 4, 2, "columns"),
                                             (128, 2, 2, 6, "columns"), (57, 2, 3, 6, "blocks"),
-                                            (64, 2, 5, 6, "blocks")])
+                                            (64, 2, 5, 6, "blocks"), (64, 4, 3, 2, "blocks")])
 def test_columns_batch_equals_single_calls(n, L, B, m, layout, policy):
     # m monomials per polynomial, fewer than a workgroup part's minimum of two
     # wavefronts' worth (lanes per monomial: 16 here in double double, 32 in
@@ -113,7 +130,7 @@ def test_columns_batch_equals_single_calls(n, L, B, m, layout, policy):
 
 
 @pytest.mark.parametrize("layout", ["columns", "blocks"])
-@pytest.mark.parametrize("name,prec", [("n8_dd", 2), ("n64_dd", 2)])
+@pytest.mark.parametrize("name,prec", [("n8_dd", 2), ("n64_dd", 2), ("n64_qd", 4)])
 def test_columns_report_singular_columns(name, prec, layout, policy):
     # t = 0, x_k = 0 (d_k >= 2), the other coordinates on the unit circle:
     # column k is the first without a nonzero pivot (in the first, a middle
@@ -145,7 +162,7 @@ def test_columns_report_nonfinite_residual(L, policy):
     x = np.zeros((16, 2, L))
     x[:, 0, 0] = 1e100
     out = {}
-    for pol in (q.ELIM_POINT, q.ELIM_COLUMNS) + ((q.ELIM_BLOCKS,) if L == 2 else ()):
+    for pol in (q.ELIM_POINT, q.ELIM_COLUMNS, q.ELIM_BLOCKS):
         policy(pol)
         say("columns non-finite h, policy", pol, "L", L)
         xg, info = q.newton_step(H, 0.5, x, L, eps=1e-10, max_it=3)
