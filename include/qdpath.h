@@ -349,14 +349,15 @@ qdp_status qdp_arith_batch(int32_t op, qdp_prec prec, int64_t count, const doubl
  *                    the pivot columns' multipliers passed through device
  *                    memory, for double and quad double, n <= 128 and
  *                    points x (n+1) <= 1024 (other calls: one per point);
- *   QDP_ELIM_BLOCKS  double and quad double, n <= 64: blocks of 16 columns
- *                    per workgroup (the register elimination inside a block,
- *                    device memory between blocks), points x blocks <= 128;
- *                    other calls as QDP_ELIM_COLUMNS;
- *   QDP_ELIM_AUTO    (default) blocks for double double at 48 < n <= 64 and
- *                    for quad double up to n = 64; columns past n = 64 (quad
- *                    double, and double double); one per point elsewhere (and
- *                    wherever the chosen layout's limits are exceeded).
+ *   QDP_ELIM_BLOCKS  double double up to n = 128, quad double up to n = 64:
+ *                    blocks of 16 columns per workgroup (the register
+ *                    elimination inside a block, device memory between
+ *                    blocks), points x blocks <= 128; other calls as
+ *                    QDP_ELIM_COLUMNS;
+ *   QDP_ELIM_AUTO    (default) blocks for double double at 48 < n <= 128 and
+ *                    for quad double up to n = 64; columns for quad double
+ *                    past n = 64; one per point elsewhere (and wherever the
+ *                    chosen layout's limits are exceeded).
  * Blocks and columns give bit for bit the same results, and so does one per
  * point where it is the register kernel (double double, n <= 64); elsewhere
  * one per point compares pivot magnitudes in full and may order near ties

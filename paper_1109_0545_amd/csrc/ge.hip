@@ -24,20 +24,22 @@ int ge_policy() { return g_ge_policy.load(); }
 bool ge_mc_possible(int L, int n, int B) {
   return (L == 2 || L == 4) && n >= 1 && n <= 128 && B >= 1 && (long)B * (n + 1) <= kMcMaxGroups;
 }
-// blocks of 16 columns per workgroup (double and quad double, n <= 64): one
-// workgroup per compute unit (its LDS), at most this many per launch
+// blocks of 16 columns per workgroup (double double up to n = 128, quad
+// double up to n = 64): one workgroup per compute unit (its LDS), at most this
+// many per launch
 constexpr long kMcbMaxGroups = 128;
 static bool ge_mcb_possible(int L, int n, int B) {
-  return (L == 2 || L == 4) && n >= 1 && n <= 64 && B >= 1 && (long)B * ((n + 16) / 16) <= kMcbMaxGroups;
+  return (L == 2 || L == 4) && n >= 1 && n <= (L == 2 ? 128 : 64) && B >= 1 &&
+         (long)B * ((n + 16) / 16) <= kMcbMaxGroups;
 }
 // policy 0 (default): blocks of columns for double double past n = 48 (four
 // blocks or more: n = 64 measured 97 us per solve against 127 us for the
-// register kernel; at n = 32 and below the register kernel is faster) and for
-// quad double up to n = 64 (n = 64: 522 us against 613 us with one workgroup
-// per column, 953 us on one CU); one workgroup per column past n = 64 (quad
-// double, and double double, whose matrix no longer fits in one compute
-// unit's registers); else one workgroup per point; 1: one per point;
-// 2: columns wherever possible; 3: blocks where possible, else as 2
+// register kernel, n = 128 294 us against 437 us with one workgroup per
+// column and 1,176 us on one CU; at n = 32 and below the register kernel is
+// faster) and for quad double up to n = 64 (n = 64: 522 us against 613 us
+// with one workgroup per column, 953 us on one CU); one workgroup per column
+// for quad double past n = 64; else one workgroup per point; 1: one per
+// point; 2: columns wherever possible; 3: blocks where possible, else as 2
 static GeMc ge_mc_choice(int L, int n, int B, double *ws) {
   const int p = g_ge_policy.load();
   if (!ws || p == 1 || !ge_mc_possible(L, n, B)) return GeMc{nullptr, 0u, 0};

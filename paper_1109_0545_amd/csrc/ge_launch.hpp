@@ -20,24 +20,30 @@ static hipError_t launch_ge_reg(int n, int B, const GeArgs<L> &a, hipStream_t s)
   return hipGetLastError();
 }
 
+// eight column wavefronts of two slots: 16 columns per block; the forwarding
+// wavefront takes up to 4 raised steps per poll (2 in quad double, for
+// registers); RPL rows per lane (2 past n = 64)
+template <int L, int RPL>
+static hipError_t launch_ge_mcb(int n, int B, const GeArgs<L> &a, const GeMc &mc, hipStream_t s) {
+  constexpr int NW = 8, CPW = 2, K = L == 4 ? 2 : 4;
+  const size_t lds = ge_mcb_lds_bytes(L, n, NW);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ge_mcb<L, NW, CPW, K, RPL>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_ge_mcb<L, NW, CPW, K, RPL>), dim3((n + NW * CPW) / (NW * CPW), B), dim3(64 * (NW + 1)), lds,
+                     s, a, mc.ws, mc.epoch);
+  return hipGetLastError();
+}
+
 template <int L>
 static hipError_t launch_ge_L(int n, int B, double *ab, double *scale, double *x, double *dz, NewtonState *st,
                               const GeMc &mc, hipStream_t s) {
   GeArgs<L> a{n, ab, scale, x, dz, st};
   if constexpr (L == 2 || L == 4) {
     if (mc.ws && mc.blocks) {
-      if (n < 1 || n > 64) return hipErrorInvalidValue;
-      // eight column wavefronts of two slots: 16 columns per block; the
-      // forwarding wavefront takes up to 4 raised steps per poll (2 in quad
-      // double, for registers)
-      constexpr int NW = 8, CPW = 2, K = L == 4 ? 2 : 4;
-      const size_t lds = ge_mcb_lds_bytes(L, n, NW);
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ge_mcb<L, NW, CPW, K>),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (e != hipSuccess) return e;
-      hipLaunchKernelGGL((k_ge_mcb<L, NW, CPW, K>), dim3((n + NW * CPW) / (NW * CPW), B), dim3(64 * (NW + 1)), lds,
-                         s, a, mc.ws, mc.epoch);
-      return hipGetLastError();
+      if (n < 1 || n > (L == 2 ? 128 : 64)) return hipErrorInvalidValue;
+      if (n <= 64) return launch_ge_mcb<L, 1>(n, B, a, mc, s);
+      if constexpr (L == 2) return launch_ge_mcb<L, 2>(n, B, a, mc, s);
     }
   }
   if constexpr (L == 2 || L == 4) {

@@ -1,7 +1,8 @@
 // Gaussian elimination with partial pivoting and back substitution of one
 // point's Newton system (Section 4, GE and Back_Subs; the solve of
 // Algorithm 4.1) in blocks of WB = NW x CPW consecutive columns, one block
-// per workgroup, for double double up to n = 64: the register kernel's
+// per workgroup (double double up to n = 128, quad double up to n = 64;
+// RPL = 2 rows per lane past n = 64): the register kernel's
 // elimination (ge_reg.hpp) inside each block, device-memory hand-offs between
 // blocks, so that the trailing updates of one point spread over several
 // compute units while the pivot chain crosses a compute unit only once per
@@ -26,9 +27,13 @@
 //     its columns are stored.
 //   * The workgroup holding column n waits for every block, copies the
 //     triangle into LDS scaled by the pivot inverses, and one wavefront
-//     back-substitutes as the register kernel does.
+//     back-substitutes as the register kernel does (past n = 64 the
+//     triangle does not fit: it is read from device memory, scaled as it
+//     arrives, the next four columns in flight, as the column-parallel
+//     kernel does).
 // Same pivots, same updates in the same order and the same substitution as
-// the register kernel, so the two agree bit for bit.  The workspace and its
+// the register kernel and the column-parallel kernel, so they agree bit for
+// bit.  The workspace and its
 // tags are those of the column-parallel kernel (ge_mc.hpp); all workgroups of
 // a launch must be resident at once, and device-memory waits are bounded.
 #pragma once
@@ -45,14 +50,18 @@ namespace qdp {
 //                         wait ran out of time)
 //   pub, rd[NW]           steps in the ring; steps read by each column wavefront
 __host__ __device__ inline constexpr int mcb_ring(int L) { return L == 4 ? 4 : KRING; }
+// (past n = 64, two rows per lane and no triangle in LDS: it is read from
+// device memory during the back substitution)
 __host__ __device__ inline size_t ge_mcb_lds_bytes(int L, int n, int NW) {
-  const size_t d = (size_t)(mcb_ring(L) * 2 * L + 2 * L) * 64 + 2 * (size_t)L * mc_tri_doubles(n);
-  return d * sizeof(double) + 64 * sizeof(int2) + (size_t)(2 + NW) * sizeof(int);
+  const size_t R = (size_t)mc_rows(n);
+  const size_t d = (size_t)(mcb_ring(L) * 2 * L + 2 * L) * R + (n <= 64 ? 2 * (size_t)L * mc_tri_doubles(n) : 0);
+  return d * sizeof(double) + R * sizeof(int2) + (size_t)(2 + NW) * sizeof(int);
 }
 
-template <int L, int NW, int CPW, int K = 4>
+template <int L, int NW, int CPW, int K = 4, int RPL = 1>
 __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *ws, unsigned epoch) {
-  constexpr int RPL = 1, RMAX = 64, E2 = 2 * L, WB = NW * CPW, KR = mcb_ring(L);
+  constexpr int RMAX = 64 * RPL, E2 = 2 * L, WB = NW * CPW, KR = mcb_ring(L);
+  constexpr bool TRI_LDS = RPL == 1;  // the gathered triangle fits in LDS
   const int n = a.n, g = blockIdx.x;
   const size_t b = blockIdx.y;
   NewtonState *const nst = a.st ? a.st + b : nullptr;
@@ -78,7 +87,7 @@ __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *w
   extern __shared__ double smem[];
   double *const ring = smem;
   double *const ltri = ring + KR * E2 * RMAX;
-  double *const rhs = ltri + E2 * TT;
+  double *const rhs = ltri + (TRI_LDS ? E2 * TT : 0);
   int2 *const ctl = reinterpret_cast<int2 *>(rhs + E2 * RMAX);
   int *const pub = reinterpret_cast<int *>(ctl + RMAX);
   int *const rd = pub + 1;
@@ -92,7 +101,11 @@ __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *w
 #pragma unroll
     for (int s = 0; s < CPW; ++s) {
       const int lc = wave + NW * s;
-      A[s][0] = (lc < ncols && lane < n) ? pload<L>(ab + (size_t)(c0 + lc) * n + lane, PS) : czero<L>();
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) {
+        const int r = lane + 64 * u;
+        A[s][u] = (lc < ncols && r < n) ? pload<L>(ab + (size_t)(c0 + lc) * n + r, PS) : czero<L>();
+      }
     }
     live = wave < ncols ? (ncols - 1 - wave) / NW + 1 : 0;
   }
@@ -110,9 +123,13 @@ __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *w
     bool fin_ok = true;
 #pragma unroll
     for (int s = 0; s < CPW; ++s)
-      if (s == sn && lane < n) {
-        hb = fmax(hb, cabs1_hi<L>(A[s][0]));
-        fin_ok = cfinite<L>(A[s][0]);
+      if (s == sn) {
+#pragma unroll
+        for (int u = 0; u < RPL; ++u)
+          if (lane + 64 * u < n) {
+            hb = fmax(hb, cabs1_hi<L>(A[s][u]));
+            fin_ok = fin_ok && cfinite<L>(A[s][u]);
+          }
       }
     const double *const scale = a.scale ? a.scale + b * n : nullptr;
     for (int r = lane; r < n; r += 64) sb = fmax(sb, scale ? scale[r] : 1.0);
@@ -125,16 +142,25 @@ __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *w
     }
   }
 
-  int mypos = n;  // pivot step of row `lane` (n while not yet a pivot row)
-  bool act = lane < n;
+  int mypos[RPL];  // pivot step of row lane + 64u (n while not yet a pivot row)
+  bool act[RPL];
+#pragma unroll
+  for (int u = 0; u < RPL; ++u) {
+    mypos[u] = n;
+    act[u] = lane + 64 * u < n;
+  }
   bool stop = false;
 
   // a column's device publication (multipliers, pivot row, inverse,
   // magnitude, flag) and its U part, unscaled, into the device triangle
-  auto publish_device = [&](int col, const C<L> &v, bool upd, int p, const C<L> &inv, double pk)
+  auto publish_device = [&](int col, const C<L>(&v)[RPL], const bool(&upd)[RPL], int p, const C<L> &inv, double pk)
                             __attribute__((always_inline)) {
     const bool sg = pk == 0.0;
-    pstore<L>(gmult + (size_t)col * E2 * RMAX + lane, RMAX, (upd && !sg && lane != p) ? v : czero<L>());
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) {
+      const int r = lane + 64 * u;
+      pstore<L>(gmult + (size_t)col * E2 * RMAX + r, RMAX, (upd[u] && !sg && r != p) ? v[u] : czero<L>());
+    }
     if (lane == 0) {
       gctl[col] = make_int2(p, sg ? 1 : 0);
       pstore<L>(ginvp + col, RMAX, inv);
@@ -142,13 +168,18 @@ __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *w
     }
     mc_raise(gpub + col, tag);
   };
-  auto store_u = [&](int col, const C<L> &v) __attribute__((always_inline)) {
-    if (mypos < col) pstore<L>(gtri + (size_t)col * (col - 1) / 2 + mypos, TT, v);
+  auto store_u = [&](int col, const C<L>(&v)[RPL]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < RPL; ++u)
+      if (mypos[u] < col) pstore<L>(gtri + (size_t)col * (col - 1) / 2 + mypos[u], TT, v[u]);
   };
   auto retire_slot0 = [&]() __attribute__((always_inline)) {
 #pragma unroll
-    for (int s = 0; s + 1 < CPW; ++s) A[s][0] = A[s + 1][0];
-    A[CPW - 1][0] = czero<L>();
+    for (int s = 0; s + 1 < CPW; ++s)
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) A[s][u] = A[s + 1][u];
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) A[CPW - 1][u] = czero<L>();
     --live;
   };
 
@@ -176,11 +207,13 @@ __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *w
       const unsigned long long nr = ~(__ballot(rdy) | 1ull);
       const int r = nr ? __builtin_ctzll(nr) : K;  // leading raised flags, >= 1
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      C<L> lk[K];
+      C<L> lk[K][RPL];
       const int2 ck = lane < r ? gctl[j + lane] : make_int2(0, 0);
 #pragma unroll
       for (int k = 0; k < K; ++k)
-        if (k < r) lk[k] = pload<L>(gmult + (size_t)(j + k) * E2 * RMAX + lane, RMAX);
+        if (k < r)
+#pragma unroll
+          for (int u = 0; u < RPL; ++u) lk[k][u] = pload<L>(gmult + (size_t)(j + k) * E2 * RMAX + lane + 64 * u, RMAX);
       bool sing = false;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
@@ -191,7 +224,8 @@ __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *w
         int rdl = lane < NW ? __hip_atomic_load(rd + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : need;
         while (__ballot(rdl < need) != 0ull)
           rdl = lane < NW ? __hip_atomic_load(rd + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : need;
-        pstore<L>(ring + (jj % KR) * E2 * RMAX + lane, RMAX, lk[k]);
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) pstore<L>(ring + (jj % KR) * E2 * RMAX + lane + 64 * u, RMAX, lk[k][u]);
         if (lane == 0) ctl[jj] = make_int2(px, py);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         if (lane == 0) __hip_atomic_store(pub, jj + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -211,16 +245,17 @@ __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *w
       C<L> inv;
       double pk;
       int p0;
-      bool cand[1] = {act};
-      reg_pivot<L, RPL>(A[0], cand, 0, ring, ctl, inv, pk, p0);
+      reg_pivot<L, RPL>(A[0], act, 0, ring, ctl, inv, pk, p0);
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
       if (lane == 0) __hip_atomic_store(pub, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      publish_device(0, A[0][0], act, p0, inv, pk);
+      publish_device(0, A[0], act, p0, inv, pk);
       retire_slot0();
     }
     bool hasdef = false;
     int pdef = 0;
-    C<L> ldef[RPL] = {czero<L>()};
+    C<L> ldef[RPL];
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) ldef[u] = czero<L>();
     auto apply = [&](const C<L> (&lm)[RPL], int ps) __attribute__((always_inline)) {
       apply_live<L, RPL, CPW>(A, live, lm, ps);
     };
@@ -234,7 +269,8 @@ __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *w
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
       const int2 cj = ctl[j];
       C<L> l[RPL];
-      l[0] = pload<L>(ring + (j % KR) * E2 * RMAX + lane, RMAX);
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) l[u] = pload<L>(ring + (j % KR) * E2 * RMAX + lane + 64 * u, RMAX);
       const int sgj = __builtin_amdgcn_readfirstlane(cj.y);
       const int p = __builtin_amdgcn_readfirstlane(cj.x);
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -243,27 +279,32 @@ __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *w
         stop = true;
         break;
       }
-      if (lane == p) mypos = j;
-      const bool upd = act && lane != p;
-      l[0] = cselect<L>(upd, l[0], czero<L>());
+      bool upd[RPL];  // rows this step updates
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) {
+        const int r = lane + 64 * u;
+        if (r == p) mypos[u] = j;
+        upd[u] = act[u] && r != p;
+        l[u] = cselect<L>(upd[u], l[u], czero<L>());
+      }
       if (owner) {
         __builtin_amdgcn_s_setprio(2);
         const int need = j1 - KR + 1;
         int rdl = lane < NW ? __hip_atomic_load(rd + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : need;
         const C<L> uv = reg_row<L, RPL>(A[0], p);
-        A[0][0] = cfms<L>(A[0][0], l[0], uv);
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) A[0][u] = cfms<L>(A[0][u], l[u], uv);
         while (__ballot(rdl < need) != 0ull)
           rdl = lane < NW ? __hip_atomic_load(rd + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) : need;
         C<L> inv;
         double pk;
         int pn;
-        bool cand[1] = {upd};
-        reg_pivot<L, RPL>(A[0], cand, j1, ring + (j1 % KR) * E2 * RMAX, ctl, inv, pk, pn);
+        reg_pivot<L, RPL>(A[0], upd, j1, ring + (j1 % KR) * E2 * RMAX, ctl, inv, pk, pn);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         if (lane == 0) __hip_atomic_store(pub, j1 + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         __builtin_amdgcn_s_setprio(0);
-        publish_device(j1, A[0][0], upd, pn, inv, pk);
-        store_u(j1, A[0][0]);
+        publish_device(j1, A[0], upd, pn, inv, pk);
+        store_u(j1, A[0]);
         retire_slot0();
         if (hasdef) {
           apply(ldef, pdef);
@@ -272,14 +313,18 @@ __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *w
         apply(l, p);
       } else if (j1 + 1 < n && owner_of(j1 + 1) == wave) {
         const C<L> uv = reg_row<L, RPL>(A[0], p);
-        A[0][0] = cfms<L>(A[0][0], l[0], uv);
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) {
+          A[0][u] = cfms<L>(A[0][u], l[u], uv);
+          ldef[u] = l[u];
+        }
         hasdef = true;
         pdef = p;
-        ldef[0] = l[0];
       } else {
         apply(l, p);
       }
-      act = upd;
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) act[u] = upd[u];
     }
     // this wavefront's device stores before the block's flag
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -339,15 +384,19 @@ __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *w
   if (ok) {
     // right-hand side (column n, slot 0 of its owner) in pivot order, scaled;
     // the triangle scaled by the pivot inverses
-    if (wave == (n - c0) % NW && mypos < n)
-      pstore<L>(rhs + mypos, RMAX, cmul<L>(A[0][0], pload<L>(ginvp + mypos, RMAX)));
-    const int ntri = n * (n - 1) / 2;
-    for (int q = tid; q < ntri; q += 64 * (NW + 1)) {
-      int c = (int)((1.0 + sqrt(1.0 + 8.0 * q)) * 0.5);
-      while (c * (c - 1) / 2 > q) --c;
-      while ((c + 1) * c / 2 <= q) ++c;
-      const int i = q - c * (c - 1) / 2;
-      pstore<L>(ltri + q, TT, cmul<L>(pload<L>(gtri + q, TT), pload<L>(ginvp + i, RMAX)));
+    if (wave == (n - c0) % NW)
+#pragma unroll
+      for (int u = 0; u < RPL; ++u)
+        if (mypos[u] < n) pstore<L>(rhs + mypos[u], RMAX, cmul<L>(A[0][u], pload<L>(ginvp + mypos[u], RMAX)));
+    if constexpr (TRI_LDS) {
+      const int ntri = n * (n - 1) / 2;
+      for (int q = tid; q < ntri; q += 64 * (NW + 1)) {
+        int c = (int)((1.0 + sqrt(1.0 + 8.0 * q)) * 0.5);
+        while (c * (c - 1) / 2 > q) --c;
+        while ((c + 1) * c / 2 <= q) ++c;
+        const int i = q - c * (c - 1) / 2;
+        pstore<L>(ltri + q, TT, cmul<L>(pload<L>(gtri + q, TT), pload<L>(ginvp + i, RMAX)));
+      }
     }
   }
   __syncthreads();
@@ -360,26 +409,72 @@ __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *w
   double *const dzp = a.dz ? a.dz + b * n * E2 : nullptr;
   double dmax = 0.0, xmax = 0.0;
   if (ok) {
-    C<L> bb = lane < n ? pload<L>(rhs + lane, RMAX) : czero<L>();
-    auto col_of = [&](int j) -> C<L> {
-      return (j >= 1 && lane < j) ? pload<L>(ltri + (size_t)j * (j - 1) / 2 + lane, TT) : czero<L>();
-    };
-    C<L> ucur = col_of(n - 1);
-    for (int j = n - 1; j > 0; --j) {
-      const C<L> unext = col_of(j - 1);
-      const C<L> xj = cbcast<L>(bb, j);
-      bb = cfms<L>(bb, ucur, xj);  // ucur is zero from row j on
-      ucur = unext;
+    C<L> bb[RPL];
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) {
+      const int k = lane + 64 * u;
+      bb[u] = k < n ? pload<L>(rhs + k, RMAX) : czero<L>();
     }
-    if (lane < n) {
-      if (dzp) cstore<L>(dzp + (size_t)lane * E2, bb);
-      if (xpt) {
-        double *xp = xpt + (size_t)lane * E2;
-        const C<L> xn = cadd<L>(cload<L>(xp), bb);
-        cstore<L>(xp, xn);
-        xmax = cabs1_hi<L>(xn);
+    if constexpr (TRI_LDS) {
+      auto col_of = [&](int j) -> C<L> {
+        return (j >= 1 && lane < j) ? pload<L>(ltri + (size_t)j * (j - 1) / 2 + lane, TT) : czero<L>();
+      };
+      C<L> ucur = col_of(n - 1);
+      for (int j = n - 1; j > 0; --j) {
+        const C<L> unext = col_of(j - 1);
+        const C<L> xj = cbcast<L>(bb[0], j);
+        bb[0] = cfms<L>(bb[0], ucur, xj);  // ucur is zero from row j on
+        ucur = unext;
       }
-      dmax = cabs1_hi<L>(bb);
+    } else {
+      // the triangle from device memory, scaled by this lane's pivot
+      // inverses as it arrives (the same products as a scaled copy), the
+      // next PF columns in flight
+      constexpr int PF = 4;
+      C<L> invk[RPL];
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) {
+        const int k = lane + 64 * u;
+        invk[u] = k < n ? pload<L>(ginvp + k, RMAX) : czero<L>();
+      }
+      auto col_of = [&](int j, C<L>(&uc)[RPL]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) {
+          const int k = lane + 64 * u;
+          uc[u] = (j >= 1 && k < j) ? pload<L>(gtri + (size_t)j * (j - 1) / 2 + k, TT) : czero<L>();
+        }
+      };
+      C<L> ring_u[PF][RPL];
+#pragma unroll
+      for (int q = 0; q < PF; ++q) col_of(n - 1 - q, ring_u[q]);
+      for (int j0 = n - 1; j0 > 0; j0 -= PF) {
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+          const int j = j0 - q;
+          if (j < 1) break;
+          const C<L> xj = reg_row<L, RPL>(bb, j);
+#pragma unroll
+          for (int u = 0; u < RPL; ++u) {
+            if (64 * u >= j) break;  // wave-uniform: no row of this slot is above j
+            bb[u] = cfms<L>(bb[u], cmul<L>(ring_u[q][u], invk[u]), xj);  // zero from row j on
+          }
+          col_of(j - PF, ring_u[q]);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) {
+      const int k = lane + 64 * u;
+      if (k < n) {
+        if (dzp) cstore<L>(dzp + (size_t)k * E2, bb[u]);
+        if (xpt) {
+          double *xp = xpt + (size_t)k * E2;
+          const C<L> xn = cadd<L>(cload<L>(xp), bb[u]);
+          cstore<L>(xp, xn);
+          xmax = fmax(xmax, cabs1_hi<L>(xn));
+        }
+        dmax = fmax(dmax, cabs1_hi<L>(bb[u]));
+      }
     }
   }
   dmax = wave_max_f64(dmax);

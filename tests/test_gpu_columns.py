@@ -55,18 +55,19 @@ def test_columns_equal_register_kernel_bit_for_bit(n, layout, policy):
     assert ip == ic, (ip, ic)
 
 
-@pytest.mark.parametrize("n", [1, 12, 17, 40, 64])
-def test_quad_double_blocks_equal_columns_bit_for_bit(n, policy):
-    # the block and column layouts in quad double: same pivots, same updates,
-    # same substitution; the default takes blocks
+@pytest.mark.parametrize("n,L", [(1, 4), (12, 4), (17, 4), (40, 4), (64, 4), (65, 2), (100, 2), (127, 2), (128, 2)])
+def test_blocks_equal_columns_bit_for_bit(n, L, policy):
+    # the block and column layouts in quad double and, past n = 64 (two rows
+    # per lane, the triangle read from device memory), double double: same
+    # pivots, same updates, same substitution; the default takes one of them
     import paper_1109_0545_amd as q
 
-    s, H = _system(n, 4, 570 + n)
-    x = random_point(n, 4, seed=580 + n, spread=0.05)
-    say("QD blocks vs columns n", n)
-    xc, ic = _step(q, H, x, 4, q.ELIM_COLUMNS, policy, 2)
-    xb, ib = _step(q, H, x, 4, q.ELIM_BLOCKS, policy, 2)
-    xa, ia = _step(q, H, x, 4, q.ELIM_AUTO, policy, 2)
+    s, H = _system(n, L, 570 + n)
+    x = random_point(n, L, seed=580 + n, spread=0.05)
+    say("blocks vs columns n", n, "L", L)
+    xc, ic = _step(q, H, x, L, q.ELIM_COLUMNS, policy, 2)
+    xb, ib = _step(q, H, x, L, q.ELIM_BLOCKS, policy, 2)
+    xa, ia = _step(q, H, x, L, q.ELIM_AUTO, policy, 2)
     assert ib["iterations"] == 2 and not ib["singular"] and not ib["nonfinite"]
     assert np.array_equal(xb, xc) and ib == ic, (ib, ic)
     assert np.array_equal(xa, xb) and ia == ib
@@ -102,7 +103,8 @@ def test_columns_agree_with_point_kernel(n, L, policy):
 
 @pytest.mark.parametrize("n,L,B,m,layout", [(57, 2, 3, 6, "columns"), (64, 4, 4, 2, "columns"),
                                             (128, 2, 2, 6, "columns"), (57, 2, 3, 6, "blocks"),
-                                            (64, 2, 5, 6, "blocks"), (64, 4, 3, 2, "blocks")])
+                                            (64, 2, 5, 6, "blocks"), (64, 4, 3, 2, "blocks"),
+                                            (128, 2, 2, 6, "blocks")])
 def test_columns_batch_equals_single_calls(n, L, B, m, layout, policy):
     # m monomials per polynomial, fewer than a workgroup part's minimum of two
     # wavefronts' worth (lanes per monomial: 16 here in double double, 32 in
@@ -130,7 +132,7 @@ def test_columns_batch_equals_single_calls(n, L, B, m, layout, policy):
 
 
 @pytest.mark.parametrize("layout", ["columns", "blocks"])
-@pytest.mark.parametrize("name,prec", [("n8_dd", 2), ("n64_dd", 2), ("n64_qd", 4)])
+@pytest.mark.parametrize("name,prec", [("n8_dd", 2), ("n64_dd", 2), ("n64_qd", 4), ("n128_dd", 2)])
 def test_columns_report_singular_columns(name, prec, layout, policy):
     # t = 0, x_k = 0 (d_k >= 2), the other coordinates on the unit circle:
     # column k is the first without a nonzero pivot (in the first, a middle
