@@ -68,3 +68,12 @@ def test_system_shapes_are_checked_before_the_library_reads_them():
 def test_noncontiguous_host_array_is_rejected():
     a = np.zeros((4, 4))[:, ::2]
     assert "contiguous" in _raises(b._ptr, a)
+
+
+def test_set_elimination_accepts_the_layouts_and_rejects_others():
+    # qdp_set_elimination only records a process-wide choice (no device call)
+    for policy in (b.ELIM_POINT, b.ELIM_COLUMNS, b.ELIM_BLOCKS, b.ELIM_AUTO):
+        b.set_elimination(policy)
+    for bad in (-1, 4):
+        assert "policy" in _raises(b.set_elimination, bad)
+    b.set_elimination(b.ELIM_AUTO)

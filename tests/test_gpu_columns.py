@@ -173,10 +173,3 @@ def test_columns_report_nonfinite_residual(L, policy):
         assert np.array_equal(xg, x)
         out[pol] = info
     assert np.isnan(out[q.ELIM_COLUMNS]["residual_first"])
-
-
-def test_set_elimination_rejects_unknown_policy():
-    import paper_1109_0545_amd as q
-
-    with pytest.raises(q.QdpError):
-        q.set_elimination(4)
