@@ -545,9 +545,10 @@ def main():
     ge_flops = (ge_cfma(n) + bs_cfma(n)) * CFMA
     ev_flops = cm * CMUL + ca * CADD
     # the elimination of one n = 64 double-double point runs in blocks of 16
-    # columns, one workgroup (one CU) per block (k_ge_mcb); the mixed solve is
-    # one workgroup
-    cus = (n + 16) // 16 if mode == 0 else 1
+    # columns, the last one taking b and up to 24 columns, one workgroup (one
+    # CU) per block (k_ge_mcb); the mixed solve is one workgroup
+    rest = n + 1 - 8
+    cus = (1 if rest <= 16 else -(-rest // 16)) if mode == 0 else 1
     if ge_us >= ev_us:
         dom = f"elimination (k_ge_mcb, {cus} workgroups)" if mode == 0 else "mixed solve (k_mixed)"
         dom_flops, dom_us = ge_flops, ge_us

@@ -20,18 +20,20 @@ static hipError_t launch_ge_reg(int n, int B, const GeArgs<L> &a, hipStream_t s)
   return hipGetLastError();
 }
 
-// eight column wavefronts of two slots: 16 columns per block; the forwarding
-// wavefront takes up to 4 raised steps per poll (2 in quad double, for
-// registers); RPL rows per lane (2 past n = 64)
+// eight column wavefronts, 16 columns per block (two slots each; in double
+// double a third slot lets the last block take up to 24 columns, so that b
+// joins the last full block: at n = 64, 4 blocks instead of 5); the
+// forwarding wavefront takes up to 4 raised steps per poll (2 in quad double,
+// for registers); RPL rows per lane (2 past n = 64)
 template <int L, int RPL>
 static hipError_t launch_ge_mcb(int n, int B, const GeArgs<L> &a, const GeMc &mc, hipStream_t s) {
-  constexpr int NW = 8, CPW = 2, K = L == 4 ? 2 : 4;
+  constexpr int NW = 8, WB = 16, CPW = L == 2 ? 3 : 2, K = L == 4 ? 2 : 4;
   const size_t lds = ge_mcb_lds_bytes(L, n, NW);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ge_mcb<L, NW, CPW, K, RPL>),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ge_mcb<L, NW, CPW, K, RPL, WB>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_ge_mcb<L, NW, CPW, K, RPL>), dim3((n + NW * CPW) / (NW * CPW), B), dim3(64 * (NW + 1)), lds,
-                     s, a, mc.ws, mc.epoch);
+  hipLaunchKernelGGL((k_ge_mcb<L, NW, CPW, K, RPL, WB>), dim3(mcb_blocks(n, WB, NW * CPW - WB), B),
+                     dim3(64 * (NW + 1)), lds, s, a, mc.ws, mc.epoch);
   return hipGetLastError();
 }
 

@@ -1,16 +1,16 @@
 // Gaussian elimination with partial pivoting and back substitution of one
 // point's Newton system (Section 4, GE and Back_Subs; the solve of
-// Algorithm 4.1) in blocks of WB = NW x CPW consecutive columns, one block
-// per workgroup (double double up to n = 128, quad double up to n = 64;
+// Algorithm 4.1) in blocks of WB consecutive columns, one block per workgroup (double double up to n = 128, quad double up to n = 64;
 // RPL = 2 rows per lane past n = 64): the register kernel's
 // elimination (ge_reg.hpp) inside each block, device-memory hand-offs between
 // blocks, so that the trailing updates of one point spread over several
 // compute units while the pivot chain crosses a compute unit only once per
 // block.
 //
-// Workgroup g holds columns g WB .. g WB + WB - 1 of [A | b] (the last one
-// ends with b = -h, column n) in NW column wavefronts (column c0 + w + NW s
-// in slot s of wavefront w, lane = row) plus one forwarding wavefront.
+// Workgroup g holds columns g WB .. g WB + WB - 1 of [A | b]; the last one
+// holds the rest, up to NW x CPW columns, ending with b = -h (column n), so
+// that b does not sit alone in a block of its own.  Column c0 + w + NW s is
+// in slot s of column wavefront w (lane = row); one more wavefront forwards.
 //   * Steps of earlier blocks: the forwarding wavefront waits for their
 //     device flags (several steps per poll when they are already raised),
 //     reads pivot rows and multipliers from device memory and places them in
@@ -52,15 +52,22 @@ namespace qdp {
 __host__ __device__ inline constexpr int mcb_ring(int L) { return L == 4 ? 4 : KRING; }
 // (past n = 64, two rows per lane and no triangle in LDS: it is read from
 // device memory during the back substitution)
+// Blocks of one point: WB columns each, the last up to WB + X (X = NW x CPW -
+// WB, its spare slots) so that b joins the last full block.
+__host__ __device__ inline int mcb_blocks(int n, int WB, int X) {
+  const int rest = n + 1 - X;
+  return rest <= WB ? 1 : (rest + WB - 1) / WB;
+}
 __host__ __device__ inline size_t ge_mcb_lds_bytes(int L, int n, int NW) {
   const size_t R = (size_t)mc_rows(n);
   const size_t d = (size_t)(mcb_ring(L) * 2 * L + 2 * L) * R + (n <= 64 ? 2 * (size_t)L * mc_tri_doubles(n) : 0);
   return d * sizeof(double) + R * sizeof(int2) + (size_t)(2 + NW) * sizeof(int);
 }
 
-template <int L, int NW, int CPW, int K = 4, int RPL = 1>
+template <int L, int NW, int CPW, int K = 4, int RPL = 1, int WB = NW * CPW>
 __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *ws, unsigned epoch) {
-  constexpr int RMAX = 64 * RPL, E2 = 2 * L, WB = NW * CPW, KR = mcb_ring(L);
+  constexpr int RMAX = 64 * RPL, E2 = 2 * L, KR = mcb_ring(L);
+  static_assert(WB <= NW * CPW, "a block fits in the slots");
   constexpr bool TRI_LDS = RPL == 1;  // the gathered triangle fits in LDS
   const int n = a.n, g = blockIdx.x;
   const size_t b = blockIdx.y;
@@ -69,9 +76,9 @@ __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *w
   const size_t PS = (size_t)n * (n + 1);
   const double *const ab = a.ab + b * E2 * PS;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int c0 = g * WB, ncols = min(WB, n + 1 - c0);
-  const bool last_wg = c0 + ncols - 1 == n;  // holds column n
-  const int G = (n + WB) / WB;                // workgroups of the point
+  const int G = mcb_blocks(n, WB, NW * CPW - WB);  // workgroups of the point
+  const int c0 = g * WB, ncols = g == G - 1 ? n + 1 - c0 : WB;
+  const bool last_wg = g == G - 1;  // holds column n
   const unsigned long long tag = kMcOk | epoch, tag_fail = kMcFail | epoch;
 
   // device workspace (layout of ge_mc_doubles; fin holds one flag per block)

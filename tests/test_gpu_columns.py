@@ -39,10 +39,11 @@ def _step(q, H, x, L, policy_value, set_policy, max_it, t=0.6):
 
 
 @pytest.mark.parametrize("layout", ["columns", "blocks"])
-@pytest.mark.parametrize("n", [1, 2, 8, 15, 16, 17, 33, 48, 57, 64])
+@pytest.mark.parametrize("n", [1, 2, 8, 15, 16, 23, 24, 33, 48, 57, 64])
 def test_columns_equal_register_kernel_bit_for_bit(n, layout, policy):
-    # blocks of 16 columns: one workgroup (n = 15), the right-hand side alone
-    # in the second (n = 16), ragged last blocks, four blocks and b (n = 64)
+    # blocks of 16 columns, the last taking up to 24 with b: one workgroup up
+    # to n = 23, two from n = 24 (the second with 9 columns), ragged last
+    # blocks, and 16 + 16 + 16 + 17 at n = 64
     import paper_1109_0545_amd as q
 
     s, H = _system(n, 2, 500 + n)
