@@ -25,8 +25,9 @@
 //   * Each finished column's U part (pivot rows, pivot order) goes to a
 //     packed triangle in device memory; a block raises its flag when all of
 //     its columns are stored.
-//   * The workgroup holding column n waits for every block, copies the
-//     triangle into LDS scaled by the pivot inverses, and one wavefront
+//   * The workgroup holding column n waits for every block (its forwarding
+//     wavefront, idle by then, gathers the earlier blocks' columns early),
+//     copies the triangle into LDS scaled by the pivot inverses, and one wavefront
 //     back-substitutes as the register kernel does (past n = 64 the
 //     triangle does not fit: it is read from device memory, scaled as it
 //     arrives, the next four columns in flight, as the column-parallel
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *w
   int *const pub = reinterpret_cast<int *>(ctl + RMAX);
   int *const rd = pub + 1;
   __shared__ double s_rho;
-  __shared__ int s_bad, s_late;
+  __shared__ int s_bad, s_late, s_fins;
 
   // ---- columns into registers
   C<L> A[CPW][RPL];
@@ -120,6 +121,7 @@ __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *w
   if (tid == 0) {
     s_bad = 0;
     s_late = 0;
+    s_fins = 1;
   }
   if (tid < NW) rd[tid] = 0;
   if (tid == 0) *pub = 0;
@@ -179,6 +181,15 @@ __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *w
 #pragma unroll
     for (int u = 0; u < RPL; ++u)
       if (mypos[u] < col) pstore<L>(gtri + (size_t)col * (col - 1) / 2 + mypos[u], TT, v[u]);
+  };
+  // packed index q = c (c - 1) / 2 + i of the triangle, i < c: entry scaled by
+  // the pivot inverse of row i, into LDS
+  auto gather_entry = [&](int q) __attribute__((always_inline)) {
+    int c = (int)((1.0 + sqrt(1.0 + 8.0 * q)) * 0.5);
+    while (c * (c - 1) / 2 > q) --c;
+    while ((c + 1) * c / 2 <= q) ++c;
+    const int i = q - c * (c - 1) / 2;
+    pstore<L>(ltri + q, TT, cmul<L>(pload<L>(gtri + q, TT), pload<L>(ginvp + i, RMAX)));
   };
   auto retire_slot0 = [&]() __attribute__((always_inline)) {
 #pragma unroll
@@ -240,6 +251,29 @@ __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *w
       }
       if (sing) break;
       j += r;
+    }
+    if (last_wg) {
+      // idle from here on: wait for the other blocks' flags (every block
+      // raises its flag, also after a stop), then gather their triangle
+      // columns into LDS while this block eliminates its own
+      bool all = true;
+      if (lane < G - 1) {
+        const unsigned long long t0 = wall_clock64();
+        unsigned long long f;
+        int it = 0;
+        while ((f = __hip_atomic_load(gfin + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != tag && f != tag_fail) {
+          if ((++it & 63) == 0 && wall_clock64() - t0 > kMcWaitTicks) break;
+          __builtin_amdgcn_s_sleep(1);
+        }
+        all = f == tag;
+      }
+      const bool fins = __ballot(!all) == 0ull;
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      if (lane == 0) s_fins = fins ? 1 : 0;
+      if constexpr (TRI_LDS) {
+        if (fins)
+          for (int q = lane; q < c0 * (c0 - 1) / 2; q += 64) gather_entry(q);
+      }
     }
   } else {
     // ---- column wavefronts
@@ -364,46 +398,26 @@ __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *w
         break;
       }
   }
-  if (ok) {
-    // other blocks' flags
-    bool all = true;
-    if (wave == 0 && lane < G - 1) {
-      const unsigned long long t0 = wall_clock64();
-      unsigned long long f;
-      int it = 0;
-      while ((f = __hip_atomic_load(gfin + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != tag && f != tag_fail) {
-        if ((++it & 63) == 0 && wall_clock64() - t0 > kMcWaitTicks) break;
-        __builtin_amdgcn_s_sleep(1);
-      }
-      all = f == tag;
-    }
-    __shared__ int s_all;
-    if (tid == 0) s_all = 1;
+  // the other blocks' flags, as the forwarding wavefront saw them (all
+  // raised, or one failed or ran out of time)
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  if (!s_fins) {
+    ok = false;
+    last = 0;
+    if (tid == 0) s_late = 1;
     __syncthreads();
-    if (wave == 0 && __ballot(!all) != 0ull && lane == 0) s_all = 0;
-    __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (!s_all) {
-      ok = false;
-      s_late = 1;
-    }
   }
   if (ok) {
     // right-hand side (column n, slot 0 of its owner) in pivot order, scaled;
-    // the triangle scaled by the pivot inverses
+    // this block's own triangle columns scaled by the pivot inverses (the
+    // earlier blocks' columns are in LDS already)
     if (wave == (n - c0) % NW)
 #pragma unroll
       for (int u = 0; u < RPL; ++u)
         if (mypos[u] < n) pstore<L>(rhs + mypos[u], RMAX, cmul<L>(A[0][u], pload<L>(ginvp + mypos[u], RMAX)));
     if constexpr (TRI_LDS) {
       const int ntri = n * (n - 1) / 2;
-      for (int q = tid; q < ntri; q += 64 * (NW + 1)) {
-        int c = (int)((1.0 + sqrt(1.0 + 8.0 * q)) * 0.5);
-        while (c * (c - 1) / 2 > q) --c;
-        while ((c + 1) * c / 2 <= q) ++c;
-        const int i = q - c * (c - 1) / 2;
-        pstore<L>(ltri + q, TT, cmul<L>(pload<L>(gtri + q, TT), pload<L>(ginvp + i, RMAX)));
-      }
+      for (int q = c0 * (c0 - 1) / 2 + tid; q < ntri; q += 64 * (NW + 1)) gather_entry(q);
     }
   }
   __syncthreads();
