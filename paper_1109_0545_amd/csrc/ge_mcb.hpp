@@ -70,6 +70,10 @@ __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *w
   constexpr int RMAX = 64 * RPL, E2 = 2 * L, KR = mcb_ring(L);
   static_assert(WB <= NW * CPW, "a block fits in the slots");
   constexpr bool TRI_LDS = RPL == 1;  // the gathered triangle fits in LDS
+  // the forwarding wavefront gathers the earlier blocks' columns while this
+  // block eliminates (double double; a quad-double entry's scaling is a
+  // ~330-instruction product that slows the pivot chain sharing its SIMD)
+  constexpr bool EARLY_GATHER = TRI_LDS && L <= 2;
   const int n = a.n, g = blockIdx.x;
   const size_t b = blockIdx.y;
   NewtonState *const nst = a.st ? a.st + b : nullptr;
@@ -270,7 +274,7 @@ __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *w
       const bool fins = __ballot(!all) == 0ull;
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       if (lane == 0) s_fins = fins ? 1 : 0;
-      if constexpr (TRI_LDS) {
+      if constexpr (EARLY_GATHER) {
         if (fins)
           for (int q = lane; q < c0 * (c0 - 1) / 2; q += 64) gather_entry(q);
       }
@@ -417,7 +421,7 @@ __global__ __launch_bounds__(64 * (NW + 1)) void k_ge_mcb(GeArgs<L> a, double *w
         if (mypos[u] < n) pstore<L>(rhs + mypos[u], RMAX, cmul<L>(A[0][u], pload<L>(ginvp + mypos[u], RMAX)));
     if constexpr (TRI_LDS) {
       const int ntri = n * (n - 1) / 2;
-      for (int q = c0 * (c0 - 1) / 2 + tid; q < ntri; q += 64 * (NW + 1)) gather_entry(q);
+      for (int q = (EARLY_GATHER ? c0 * (c0 - 1) / 2 : 0) + tid; q < ntri; q += 64 * (NW + 1)) gather_entry(q);
     }
   }
   __syncthreads();
