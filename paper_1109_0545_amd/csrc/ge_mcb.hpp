@@ -1,11 +1,11 @@
 // Gaussian elimination with partial pivoting and back substitution of one
 // point's Newton system (Section 4, GE and Back_Subs; the solve of
-// Algorithm 4.1) in blocks of WB consecutive columns, one block per workgroup (double double up to n = 128, quad double up to n = 64;
-// RPL = 2 rows per lane past n = 64): the register kernel's
-// elimination (ge_reg.hpp) inside each block, device-memory hand-offs between
-// blocks, so that the trailing updates of one point spread over several
-// compute units while the pivot chain crosses a compute unit only once per
-// block.
+// Algorithm 4.1) in blocks of WB consecutive columns, one block per
+// workgroup (double double up to n = 128, quad double up to n = 64; RPL = 2
+// rows per lane past n = 64): the register kernel's elimination (ge_reg.hpp)
+// inside each block, device-memory hand-offs between blocks, so that the
+// trailing updates of one point spread over several compute units while the
+// pivot chain crosses a compute unit only once per block.
 //
 // Workgroup g holds columns g WB .. g WB + WB - 1 of [A | b]; the last one
 // holds the rest, up to NW x CPW columns, ending with b = -h (column n), so
@@ -26,33 +26,33 @@
 //     packed triangle in device memory; a block raises its flag when all of
 //     its columns are stored.
 //   * The workgroup holding column n waits for every block (its forwarding
-//     wavefront, idle by then, gathers the earlier blocks' columns early),
-//     copies the triangle into LDS scaled by the pivot inverses, and one wavefront
-//     back-substitutes as the register kernel does (past n = 64 the
-//     triangle does not fit: it is read from device memory, scaled as it
-//     arrives, the next four columns in flight, as the column-parallel
-//     kernel does).
+//     wavefront, idle by then, waits for their flags and, in double double,
+//     gathers their columns early), copies the triangle into LDS scaled by
+//     the pivot inverses, and one wavefront back-substitutes as the register
+//     kernel does (past n = 64 the triangle does not fit: it is read from
+//     device memory, scaled as it arrives, the next four columns in flight,
+//     as the column-parallel kernel does).
 // Same pivots, same updates in the same order and the same substitution as
 // the register kernel and the column-parallel kernel, so they agree bit for
-// bit.  The workspace and its
-// tags are those of the column-parallel kernel (ge_mc.hpp); all workgroups of
-// a launch must be resident at once, and device-memory waits are bounded.
+// bit.  The workspace and its tags are those of the column-parallel kernel
+// (ge_mc.hpp); all workgroups of a launch must be resident at once, and
+// device-memory waits are bounded.
 #pragma once
 #include "ge_mc.hpp"
 
 namespace qdp {
 
 // LDS of one block workgroup, in doubles (then ints):
-//   ring [KR][2L][64]     multipliers of the last KR steps (KR = 8, 4 in quad
+//   ring [KR][2L][R]      multipliers of the last KR steps (KR = 8, 4 in quad
 //                         double, whose gathered triangle takes 129 KB at n = 64)
-//   tri  [2L][TT]         (last block) scaled U, packed by columns
-//   rhs  [2L][64]         (last block) scaled right-hand side, pivot order
-//   ctl  [64] int2        pivot row and flag of every step (flag 2: a device
+//   tri  [2L][TT]         (last block, n <= 64) scaled U, packed by columns;
+//                         past n = 64 it is read from device memory instead
+//   rhs  [2L][R]          (last block) scaled right-hand side, pivot order
+//   ctl  [R] int2         pivot row and flag of every step (flag 2: a device
 //                         wait ran out of time)
 //   pub, rd[NW]           steps in the ring; steps read by each column wavefront
+// (R = 64 rows, 128 past n = 64)
 __host__ __device__ inline constexpr int mcb_ring(int L) { return L == 4 ? 4 : KRING; }
-// (past n = 64, two rows per lane and no triangle in LDS: it is read from
-// device memory during the back substitution)
 // Blocks of one point: WB columns each, the last up to WB + X (X = NW x CPW -
 // WB, its spare slots) so that b joins the last full block.
 __host__ __device__ inline int mcb_blocks(int n, int WB, int X) {
