@@ -496,8 +496,10 @@ def main():
     ap.add_argument("--profile-line", choices=["n64_dd", "n128_dd", "n64_qd"],
                     help="run only this one-path Newton line (--mode, --steps iterations) and print its rates "
                          "(for profiling the mixed-precision and quad-double kernels)")
+    ap.add_argument("--batch-workload", choices=["n64_dd", "n64_qd"], default="n64_dd",
+                    help="workload of --profile-batch")
     ap.add_argument("--profile-batch", action="store_true",
-                    help="run only the batched Newton line (n=64 double double, --batch points per launch, "
+                    help="run only the batched Newton line (--batch-workload, --batch points per launch, "
                          "--steps iterations) and print its rates (for profiling the batched evaluation)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -535,8 +537,10 @@ def main():
         print(json.dumps(common_support_case(q, steps=args.steps)))
         return
     if args.profile_batch:
-        r = newton_rate(q, "n64_dd", L, mode, args.steps, args.warmup, t, B=args.batch)
-        print(json.dumps(rate_entry("n64_dd", L, args.batch, mode, *r[:5])))
+        wl = args.batch_workload
+        lim = 4 if wl.endswith("qd") else 2
+        r = newton_rate(q, wl, lim, mode, args.steps, args.warmup, t, B=args.batch)
+        print(json.dumps(rate_entry(wl, lim, args.batch, mode, *r[:5])))
         return
     rate, ms, ev_us, ge_us, sysm, info = newton_rate(q, "n64_dd", L, mode, args.steps, args.warmup, t)
 
