@@ -21,13 +21,16 @@ static hipError_t launch_ge_reg(int n, int B, const GeArgs<L> &a, hipStream_t s)
 }
 
 // eight column wavefronts, 16 columns per block (two slots each; in double
-// double a third slot lets the last block take up to 24 columns, so that b
-// joins the last full block: at n = 64, 4 blocks instead of 5); the
-// forwarding wavefront takes up to 4 raised steps per poll (2 in quad double,
-// for registers); RPL rows per lane (2 past n = 64)
+// double with one row per lane a third slot lets the last block take up to
+// 24 columns, so that b joins the last full block: at n = 64, 4 blocks
+// instead of 5, 95.2 -> 92.5 us; with two rows per lane, or in quad double,
+// the third slot measured slower: n = 128 DD 302.6 against 292.3 us, n = 64
+// QD 583 against 508 us); the forwarding wavefront takes up to 4 raised
+// steps per poll (2 in quad double, for registers); RPL rows per lane (2 past
+// n = 64)
 template <int L, int RPL>
 static hipError_t launch_ge_mcb(int n, int B, const GeArgs<L> &a, const GeMc &mc, hipStream_t s) {
-  constexpr int NW = 8, WB = 16, CPW = L == 2 ? 3 : 2, K = L == 4 ? 2 : 4;
+  constexpr int NW = 8, WB = 16, CPW = (L == 2 && RPL == 1) ? 3 : 2, K = L == 4 ? 2 : 4;
   const size_t lds = ge_mcb_lds_bytes(L, n, NW);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ge_mcb<L, NW, CPW, K, RPL, WB>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
